@@ -1,0 +1,107 @@
+"""Pins of the oracle's discrete adjoint of RKC (the accepted-step map with step
+sizes and stage counts held fixed) against closed forms on linear problems and
+central finite differences of the frozen replay."""
+import mpmath as mp
+import numpy as np
+import pytest
+
+from paper_1611_02274_amd import inputs as I
+
+from .test_oracle_rkc import P_closed
+
+
+def test_scalar_linear_closed_form(orc):
+    """y' = lam y: every step multiplies by P_s(h lam), so
+    dL/dy0 = w prod_k P_{s_k}(h_k lam)."""
+    lam = -2.0e4
+    pb = orc.linear([[lam]])
+    y1, st, stats, hs, ss = orc.rkc_solve(pb, None, [1.0], 0.0, 1e-3, 1e-6, 1e-10)
+    assert st == orc.OK and len(hs) > 3
+    w = 0.7
+    dy0, dth = orc.rkc_replay_adjoint(pb, None, [1.0], 0.0, hs, ss, [w])
+    prod = mp.mpf(1)
+    for h, s in zip(hs, ss):
+        prod *= P_closed(int(s), h * lam)[0]
+    assert dy0[0] == pytest.approx(float(w * prod), rel=1e-10)
+    assert y1[0] == pytest.approx(float(prod), rel=1e-10)
+
+
+def test_matrix_linear_closed_form(orc):
+    """y' = A y (symmetric A): the step map is P_s(h A), so
+    dL/dy0 = (prod_k P_{s_k}(h_k A))^T w, evaluated in the eigenbasis."""
+    eigs = [-1.0, -30.0, -500.0, -4.0e5]
+    A = I.linear_problem_matrix(eigs, seed=9)
+    pb = orc.linear(A)
+    y0 = np.array([0.3, -1.0, 0.5, 2.0])
+    y1, st, stats, hs, ss = orc.rkc_solve(pb, None, y0, 0.0, 0.01, 1e-7, 1e-10)
+    assert st == orc.OK and ss.max() > 4
+    lam, Q = np.linalg.eigh(A)
+    m = np.ones(len(eigs))
+    for h, s in zip(hs, ss):
+        m *= np.array([float(P_closed(int(s), h * l)[0]) for l in lam])
+    M = Q @ np.diag(m) @ Q.T
+    w = np.array([1.0, 0.2, -0.4, 0.9])
+    dy0, _ = orc.rkc_replay_adjoint(pb, None, y0, 0.0, hs, ss, w)
+    assert np.allclose(dy0, M.T @ w, rtol=1e-9, atol=1e-12)
+    assert np.allclose(y1, M @ y0, rtol=1e-9, atol=1e-12)
+
+
+def _loss(orc, pb, g, y0, hs, ss, w):
+    return float(w @ orc.rkc_replay(pb, g, y0, 0.0, hs, ss))
+
+
+def test_vdp_adjoint_vs_fd(orc):
+    pb = orc.vdp()
+    mu, y0 = np.array([1.3]), np.array([1.0, -0.5])
+    _, st, _, hs, ss = orc.rkc_solve(pb, mu, y0, 0.0, 2.0, 1e-6, 1e-8)
+    w = np.array([0.4, -1.1])
+    dy0, dmu = orc.rkc_replay_adjoint(pb, mu, y0, 0.0, hs, ss, w)
+    e = 1e-6
+    for m in range(2):
+        d = np.zeros(2)
+        d[m] = e
+        fd = (_loss(orc, pb, mu, y0 + d, hs, ss, w) - _loss(orc, pb, mu, y0 - d, hs, ss, w)) / (2 * e)
+        assert dy0[m] == pytest.approx(fd, rel=1e-7)
+    fd = (_loss(orc, pb, mu + e, y0, hs, ss, w) - _loss(orc, pb, mu - e, y0, hs, ss, w)) / (2 * e)
+    assert dmu[0] == pytest.approx(fd, rel=1e-7)
+
+
+def test_network_adjoint_vs_fd(orc):
+    """13-species network, loss w . y(t1): dL/dY0 and dL/dlnA against central
+    differences (absolute step 1e-6) of the replayed step sequence."""
+    net = I.standard_network(13)
+    pb = orc.network(net)
+    y0, g = I.kinetics_inputs(net, 2, 5005)
+    w = I.adjoint_weights(13, 2, 5005)
+    for i in range(2):
+        yi, gi, wi = y0[:, i], g[:, i], w[:, i]
+        _, st, _, hs, ss = orc.rkc_solve(pb, gi, yi, 0.0, 1e-7, 1e-8, 1e-12)
+        assert st == orc.OK
+        dy0, dlnA = orc.rkc_replay_adjoint(pb, gi, yi, 0.0, hs, ss, wi)
+        e = 1e-6
+        for m in range(13):
+            d = np.zeros(13)
+            d[m] = e
+            fd = (_loss(orc, pb, gi, yi + d, hs, ss, wi) -
+                  _loss(orc, pb, gi, yi - d, hs, ss, wi)) / (2 * e)
+            assert dy0[m] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(dy0).max())
+        for j in range(0, net.n_rx, 3):
+            d = np.zeros(net.n_rx)
+            d[j] = e
+            fp = _loss(orc, pb.with_lnA(net.lnA + d), gi, yi, hs, ss, wi)
+            fm = _loss(orc, pb.with_lnA(net.lnA - d), gi, yi, hs, ss, wi)
+            fd = (fp - fm) / (2 * e)
+            assert dlnA[j] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(dlnA).max())
+
+
+def test_adjoint_batch_matches_single(orc):
+    net = I.standard_network(13)
+    pb = orc.network(net)
+    y0, g = I.kinetics_inputs(net, 4, 5005)
+    w = I.adjoint_weights(13, 4, 5005)
+    y1, dy0, dth, status = orc.rkc_adjoint_batch(pb, y0, g, w, 0.0, 2e-8, 1e-8, 1e-12)
+    assert np.all(status == 0)
+    for i in (0, 3):
+        _, _, _, hs, ss = orc.rkc_solve(pb, g[:, i], y0[:, i], 0.0, 2e-8, 1e-8, 1e-12)
+        d0, dl = orc.rkc_replay_adjoint(pb, g[:, i], y0[:, i], 0.0, hs, ss, w[:, i])
+        assert np.array_equal(d0, dy0[:, i]) and np.array_equal(dl, dth[:, i])
