@@ -82,6 +82,9 @@ def lib():
                                                 C.c_double, C.c_double, C.c_int64, _dp, _dp, _dp,
                                                 _dp, _ip, C.c_int]),
             "orc_max_threads": (C.c_int, []),
+            "orc_cr_exp": (C.c_double, [C.c_double]),
+            "orc_cr_log": (C.c_double, [C.c_double]),
+            "orc_cr_pow": (C.c_double, [C.c_double, C.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -331,6 +334,18 @@ def rkc_adjoint_batch(pb, y0, g, w, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_ST
                                      _d(w), _d(y1), _d(dy0), _d(dth), _i(status), n_threads)
     assert rc == 0, rc
     return y1, dy0, dth[:pb.n_theta], status
+
+
+def cr_exp(x):
+    return lib().orc_cr_exp(float(x))
+
+
+def cr_log(x):
+    return lib().orc_cr_log(float(x))
+
+
+def cr_pow(x, y):
+    return lib().orc_cr_pow(float(x), float(y))
 
 
 def max_threads():

@@ -11,11 +11,37 @@
 #include "rk_oracle.h"
 
 #include <math.h>
+#include <quadmath.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* ------------------------------------------------------- transcendentals
+ * Reading: the paper does not say how accurately exp, log and pow are
+ * evaluated.  Step-size and stage-count decisions hinge on their last bit, so
+ * the oracle evaluates each one correctly rounded: the exact value rounded to
+ * the nearest double, obtained by evaluating in IEEE binary128 (libquadmath)
+ * and rounding once to double.  Special values follow C99 Annex F. */
+double orc_cr_exp(double x) {
+  if (isnan(x)) return x;
+  return (double)expq((__float128)x);
+}
+
+double orc_cr_log(double x) {
+  if (isnan(x)) return x;
+  if (x < 0.0) return NAN;
+  if (x == 0.0) return -INFINITY;
+  if (isinf(x)) return x;
+  return (double)logq((__float128)x);
+}
+
+double orc_cr_pow(double x, double y) {
+  if (y == 0.0 || x == 1.0) return 1.0;
+  if (isnan(x) || isnan(y)) return x + y;
+  return (double)powq((__float128)x, (__float128)y);
+}
 
 /* Constants of the RKCK driver (Sec. 3.1 constant list). */
 #define UROUND 2.22e-16
@@ -38,7 +64,8 @@ typedef struct {
   double g[ORC_MAXP];
   double kf[ORC_MAXR];
   double kr[ORC_MAXR];
-  double rho;
+  double invW[ORC_MAXN];
+  double rho, irho;
 } orc_sys;
 
 static int check_problem(const orc_problem *pb) {
@@ -55,17 +82,21 @@ static int check_problem(const orc_problem *pb) {
 }
 
 /* Arrhenius rate coefficient k = A T^beta exp(-E/T) (Sec. 4.2), evaluated in
- * log form so that ln A enters additively; reverse k_r = k_f / K. */
+ * log form so that ln A enters additively; reverse k_r = k_f / K.  The
+ * divisions by the constants K_j, W_k and rho are written as multiplications
+ * by their reciprocals, each formed once (per network or per system). */
 static void sys_init(orc_sys *S, const orc_problem *pb, const double *g) {
   S->pb = pb;
   for (int i = 0; i < pb->n_param; ++i) S->g[i] = g[i];
   if (pb->kind == ORC_MASS_ACTION) {
     double T = g[0];
-    double lnT = log(T);
+    double lnT = orc_cr_log(T);
     S->rho = g[1];
+    S->irho = 1.0 / S->rho;
+    for (int k = 0; k < pb->n_eq; ++k) S->invW[k] = 1.0 / pb->W[k];
     for (int j = 0; j < pb->n_rx; ++j) {
-      S->kf[j] = exp(pb->lnA[j] + pb->beta[j] * lnT - pb->Ea[j] / T);
-      S->kr[j] = S->kf[j] / pb->Keq[j];
+      S->kf[j] = orc_cr_exp(pb->lnA[j] + pb->beta[j] * lnT - pb->Ea[j] / T);
+      S->kr[j] = S->kf[j] * (1.0 / pb->Keq[j]);
     }
   }
 }
@@ -92,7 +123,7 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
      * a one-species side multiplied by the total concentration [M]. */
     double C[ORC_MAXN], omega[ORC_MAXN];
     double M = 0.0;
-    for (int k = 0; k < N; ++k) C[k] = S->rho * y[k] / pb->W[k];
+    for (int k = 0; k < N; ++k) C[k] = (S->rho * S->invW[k]) * y[k];
     for (int k = 0; k < N; ++k) M += C[k];
     for (int k = 0; k < N; ++k) omega[k] = 0.0;
     for (int j = 0; j < pb->n_rx; ++j) {
@@ -106,7 +137,7 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
       omega[p0] += q;
       if (p1 >= 0) omega[p1] += q;
     }
-    for (int k = 0; k < N; ++k) f[k] = pb->W[k] * omega[k] / S->rho;
+    for (int k = 0; k < N; ++k) f[k] = (pb->W[k] * S->irho) * omega[k];
   }
 }
 
@@ -137,10 +168,10 @@ static void rhs_vjp(const orc_sys *S, const double *y, const double *u, double *
   } else {
     double C[ORC_MAXN], uw[ORC_MAXN], Cbar[ORC_MAXN];
     double M = 0.0, Mbar = 0.0;
-    for (int k = 0; k < N; ++k) C[k] = S->rho * y[k] / pb->W[k];
+    for (int k = 0; k < N; ++k) C[k] = (S->rho * S->invW[k]) * y[k];
     for (int k = 0; k < N; ++k) M += C[k];
     /* u^T f = sum_k (W_k/rho) u_k omega_k */
-    for (int k = 0; k < N; ++k) uw[k] = pb->W[k] * u[k] / S->rho;
+    for (int k = 0; k < N; ++k) uw[k] = (pb->W[k] * S->irho) * u[k];
     for (int k = 0; k < N; ++k) Cbar[k] = 0.0;
     for (int j = 0; j < pb->n_rx; ++j) {
       int r0 = pb->reac[2 * j], r1 = pb->reac[2 * j + 1];
@@ -170,7 +201,7 @@ static void rhs_vjp(const orc_sys *S, const double *y, const double *u, double *
       }
     }
     /* d M / d C_k = 1, d C_k / d y_k = rho / W_k */
-    for (int k = 0; k < N; ++k) jtu[k] = (Cbar[k] + Mbar) * S->rho / pb->W[k];
+    for (int k = 0; k < N; ++k) jtu[k] = (S->rho * S->invW[k]) * (Cbar[k] + Mbar);
   }
 }
 
@@ -251,12 +282,16 @@ static void rkck_trial(const orc_sys *S, double t, const double *y, const double
     rhs(S, t + RKCK_A[s] * h, z, f);
     for (int i = 0; i < N; ++i) k[s][i] = h * f[i];
   }
+  /* weights that are zero in Table 1 (c_2, c_5, and c_2 - c*_2) contribute
+   * nothing and are skipped */
   for (int i = 0; i < N; ++i) {
     double acc = y[i];
-    for (int s = 0; s < 6; ++s) acc = acc + RKCK_C[s] * k[s][i];
+    for (int s = 0; s < 6; ++s)
+      if (RKCK_C[s] != 0.0) acc = acc + RKCK_C[s] * k[s][i];
     ytemp[i] = acc;
     double e = 0.0;
-    for (int s = 0; s < 6; ++s) e = e + RKCK_E[s] * k[s][i];
+    for (int s = 0; s < 6; ++s)
+      if (RKCK_E[s] != 0.0) e = e + RKCK_E[s] * k[s][i];
     yerr[i] = e;
   }
 }
@@ -300,12 +335,12 @@ double orc_rkck_control(double err, int nan_flag, double h, double hmin, double 
   if ((err > 1.0) || isnan(err) || nan_flag) {
     *accept = 0;
     if (isnan(err) || nan_flag) return h * P1;
-    return fmax(SAFETY * h * pow(err, PSHRNK), P1 * h);
+    return fmax(SAFETY * h * orc_cr_pow(err, PSHRNK), P1 * h);
   }
   *accept = 1;
   double hn;
   if (err > ERRCON)
-    hn = SAFETY * h * pow(err, PGROW);
+    hn = SAFETY * h * orc_cr_pow(err, PGROW);
   else
     hn = h * 5.0;
   return fmax(hmin, fmin(hmax, hn));
@@ -640,11 +675,11 @@ double orc_rkc_accept_factor(double err, double err_prev, double h, double h_pre
                              int have_prev) {
   double fac = 10.0;
   if (!have_prev) {
-    double t2 = pow(err, 1.0 / 3.0);
+    double t2 = orc_cr_pow(err, 1.0 / 3.0);
     if (0.8 < fac * t2) fac = 0.8 / t2;
   } else {
-    double t1 = 0.8 * h * pow(err_prev, 1.0 / 3.0);
-    double t2 = h_prev * pow(err, 2.0 / 3.0);
+    double t1 = 0.8 * h * orc_cr_pow(err_prev, 1.0 / 3.0);
+    double t2 = h_prev * orc_cr_pow(err, 2.0 / 3.0);
     if (t1 < fac * t2) fac = t1 / t2;
   }
   return fac;
@@ -701,7 +736,10 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
   const double hmax = fabs(t1 - t0);
   const double hmin = 10.0 * UROUND * fmax(fabs(t0), hmax);
   double t = t0;
-  for (int i = 0; i < N; ++i) y_n[i] = y0[i];
+  for (int i = 0; i < N; ++i) {
+    y_n[i] = y0[i];
+    F_n[i] = 0.0;
+  }
   int64_t n_acc = 0, n_rej = 0, n_rhs = 0, n_sr = 0, n_pow = 0, attempts = 0;
   int max_m = 0, status = ORC_OK;
   if (t < t1) {
@@ -767,7 +805,7 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
     if (err > 1.0 || !isfinite(err)) {
       n_rej++;
       if (isfinite(err))
-        h = 0.8 * h / pow(err, 1.0 / 3.0);
+        h = 0.8 * h / orc_cr_pow(err, 1.0 / 3.0);
       else
         h = P1 * h;
       int it = 0;

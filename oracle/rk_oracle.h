@@ -65,6 +65,10 @@ extern "C" {
 #endif
 
 /* ---- building blocks (exported so the tests can pin each one) ---- */
+/* exp, log and pow correctly rounded (evaluated in binary128, rounded once) */
+double orc_cr_exp(double x);
+double orc_cr_log(double x);
+double orc_cr_pow(double x, double y);
 int  orc_n_theta(const orc_problem *pb);
 void orc_rkck_tableau(double a[6], double b[36], double c[6], double cs[6], double e[6]);
 int  orc_rhs(const orc_problem *pb, const double *g, double t, const double *y, double *f);
