@@ -1,0 +1,148 @@
+"""Benchmark: batched FP64 ODE integration on one MI355X.
+
+One step = one full integration of every system of the workload from t0 to t1
+(all of the hot path: SoA load, rate setup, RHS, stages, error control,
+power method, store), inputs resident in device memory.  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload net13_rkc]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ODE systems integrated/sec at rtol 1e-8 (RKCK, RKC) vs FP64 roofline; adjoint grads/s"
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 128 FP64 flop/clk x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, net, y0, g, target_s: float):
+    """The oracle (serial per system, OpenMP across systems) on a bounded sample."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    pb = orc.vdp() if net is None else orc.network(net)
+    fn = orc.rkck_batch if w.method == "rkck" else orc.rkc_batch
+    cores = orc.max_threads()
+
+    def run(m):
+        idx = np.unique(np.linspace(0, w.n - 1, m).astype(np.int64))
+        ys, gs = np.ascontiguousarray(y0[:, idx]), np.ascontiguousarray(g[:, idx])
+        t = time.perf_counter()
+        fn(pb, ys, gs, w.t0, w.t1, w.rtol, w.atol)
+        return len(idx), time.perf_counter() - t
+
+    m, dt = run(min(w.n, max(64, 8 * cores)))
+    if dt < target_s and m < w.n:
+        want = int(m * target_s / max(dt, 1e-6))
+        m, dt = run(min(w.n, max(m, want)))
+    return {"value": m / dt, "unit": "systems/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m} of {w.n} systems (evenly spaced), {dt:.1f} s on {cores} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="net13_rkc")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the systems are "
+              "independent, so a multi-GPU run is one shard per GPU with no exchange",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1611_02274_amd as rk
+    from paper_1611_02274_amd import flops as FL
+    from paper_1611_02274_amd import inputs as I
+
+    w = I.WORKLOADS[args.workload]
+    net = None if w.problem == "vdp" else I.network_of(w.problem)
+    log(f"bench: workload {w.name} n={w.n}; generating inputs")
+    y0, g = I.workload_inputs(w)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = rk.Problem.vdp() if net is None else rk.Problem.network(net)
+    yd, gd = torch.from_numpy(y0).to(dev), torch.from_numpy(g).to(dev)
+    out = torch.empty_like(yd)
+    status = torch.empty(w.n, dtype=torch.int32, device=dev)
+    stats = torch.empty((rk.RK_NSTATS, w.n), dtype=torch.int32, device=dev)
+    fn = rk.integrate_rkck if w.method == "rkck" else rk.integrate_rkc
+
+    def step():
+        fn(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, out=out, status=status, stats=stats)
+
+    for k in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {k + 1}/{args.warmup} done")
+    stream = torch.cuda.current_stream(dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s, kernel {kern_ms:.3f} ms/launch")
+
+    st_h = stats.cpu().numpy()
+    status_h = status.cpu().numpy()
+    flops = FL.total(w.method, st_h, prob.n_eq, net)
+    achieved = flops / (kern_ms * 1e-3) / 1e12
+    value = w.n * args.steps / elapsed
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name, "method": w.method, "problem": w.problem, "n_systems": w.n,
+            "t0": w.t0, "t1": w.t1, "rtol": w.rtol, "atol": w.atol,
+            "kernel": "plain (one system per lane)",
+            "systems_ok": int((status_h == 0).sum()),
+            "mean_accepted_steps": float(st_h[0].mean()),
+            "mean_rhs_evals": float(st_h[2].mean()),
+        },
+        "roofline": {
+            "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a sample")
+        res["cpu_baseline"] = cpu_baseline(w, net, y0, g, args.cpu_seconds)
+        res["cpu_baseline"]["gpu_speedup"] = value / res["cpu_baseline"]["value"]
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/*
+ * rkmi.h -- C ABI of the MI355X batched ODE integrators.
+ *
+ * Integrates very many independent ODE systems dy/dt = f(t, y, g), each with
+ * its own initial state y(t0) and constant parameters g, from t0 to t1
+ * (Niemeyer & Sung 2014, Sec. 2, Eq. 1), by
+ *   - RKCK: adaptive fifth-order Runge-Kutta-Cash-Karp (Sec. 2.1, Table 1,
+ *     driver of Sec. 3.1), for nonstiff systems;
+ *   - RKC: adaptive second-order Runge-Kutta-Chebyshev (Sec. 2.2, driver of
+ *     Sec. 3.2, nonlinear power method of the Appendix), for moderately stiff
+ *     systems.
+ * Every call restarts the integrator (Sec. 3: no step-size memory between
+ * calls), as an operator-split caller needs.
+ *
+ * Conventions for every entry point:
+ *   - Arrays are FP64 (states, parameters) or int32 (status, statistics),
+ *     struct-of-arrays: element (row r, system i) sits at [r * n_sys + i], so
+ *     the same unknown of consecutive systems is contiguous (Sec. 3).
+ *   - Array arguments are DEVICE pointers on the current HIP device, owned by
+ *     the caller, 8-byte aligned (4 for int32).  The library checks that each
+ *     is device memory but cannot check its extent: the caller guarantees the
+ *     sizes stated per argument.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     the call returns without waiting.  Outputs are valid once the stream has
+ *     reached that point.
+ *   - Return value: RK_OK, or a negative RK_E* code when the arguments are
+ *     rejected or the launch fails; then nothing was enqueued (launch failures
+ *     excepted) and rk_last_error() describes the problem.
+ *   - Numerical failure of a single system is not an error of the call: it
+ *     is reported in that system's `status` entry; its output is the last
+ *     accepted state and the other systems are unaffected.
+ */
+#ifndef RKMI_H
+#define RKMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define RK_OK 0
+#define RK_EINVAL (-1)        /* invalid argument */
+#define RK_ENOMEM (-2)        /* host or device allocation failed */
+#define RK_EHIP (-3)          /* HIP runtime or launch error */
+#define RK_EUNSUPPORTED (-4)  /* no compiled code for this problem / method */
+#define RK_EWORKSPACE (-5)    /* workspace missing or too small */
+
+/* Per-system status. */
+#define RK_SYS_OK 0
+#define RK_SYS_NONFINITE 1    /* an accepted state was not finite */
+#define RK_SYS_HMIN 2         /* step fell below the minimum after a rejection */
+#define RK_SYS_MAXSTEPS 3     /* max_steps attempts used before reaching t1 */
+
+/* Rows of the per-system statistics array. */
+#define RK_STAT_ACCEPT 0      /* accepted steps */
+#define RK_STAT_REJECT 1      /* rejected attempts */
+#define RK_STAT_RHS 2         /* right-hand-side evaluations */
+#define RK_STAT_SR_CALLS 3    /* spectral-radius estimates (RKC) */
+#define RK_STAT_POW_ITERS 4   /* power-method iterations (RKC) */
+#define RK_STAT_MAX_STAGES 5  /* largest stage count used (RKC; 6 for RKCK) */
+#define RK_NSTATS 6
+
+typedef struct rk_problem_s *rk_problem;
+
+/* A reversible mass-action network (host arrays, copied by the library).
+ * Rate law, isothermal at constant volume (Sec. 4.2 species equations):
+ *   C_k = rho Y_k / W_k,  [M] = sum_k C_k,
+ *   k_f,j = exp(lnA_j + beta_j ln T - Ea_j / T),   k_r,j = k_f,j / Keq_j
+ *   (Sec. 4.2 Arrhenius form, Ea in kelvin, i.e. E/R),
+ *   q_j = k_f,j prod_{reactant slots} C - k_r,j prod_{product slots} C,
+ *         where a side with a single species is multiplied by [M],
+ *   dY_k/dt = (W_k / rho) sum_j nu_kj q_j.
+ * reac/prod: [n_rx][2] species indices in [0, n_sp), second slot -1 for a
+ * one-species side.  Per-system parameters g = (T, rho): rows 0 and 1. */
+typedef struct {
+  int32_t n_sp;
+  int32_t n_rx;
+  const int32_t *reac;
+  const int32_t *prod;
+  const double *lnA;    /* [n_rx] */
+  const double *beta;   /* [n_rx] */
+  const double *Ea;     /* [n_rx] kelvin */
+  const double *Keq;    /* [n_rx] > 0 */
+  const double *W;      /* [n_sp] > 0 */
+} rk_mech_desc;
+
+/* Options; pass NULL for the defaults of the paper's listings. */
+typedef struct {
+  int64_t max_steps;    /* attempts per system before RK_SYS_MAXSTEPS; <= 0: 10^7 */
+  int32_t sr_period;    /* RKC: spectral radius every this many accepted steps; <= 0: 25 */
+  int32_t sr_itmax;     /* RKC: power-method iteration limit; <= 0: 50 */
+  int32_t schedule;     /* 0: automatic; 1: plain one-lane-per-system kernel */
+  int32_t reserved[7];  /* set to 0 */
+} rk_options;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int rk_version(void);
+
+/* Message describing the last failed call on this host thread ("" if none). */
+const char *rk_last_error(void);
+
+/* Van der Pol oscillators (Sec. 2 Eq. 1 with N = 2): f = (y2, mu (1 - y1^2) y2 - y1);
+ * one parameter per system, g row 0 = mu.  *out receives a handle to release
+ * with rk_problem_destroy. */
+int rk_problem_create_vdp(rk_problem *out);
+
+/* Mass-action network described by *desc (host memory, copied).  The network
+ * topology must have been compiled into the library (see the package's code
+ * generator); RK_EUNSUPPORTED otherwise. */
+int rk_problem_create_mass_action(const rk_mech_desc *desc, rk_problem *out);
+
+/* Releases a problem handle and its device copies (NULL is ignored).  No
+ * integration using it may still be pending on any stream. */
+void rk_problem_destroy(rk_problem p);
+
+/* Unknowns per system, parameters per system (rows of g), and differentiable
+ * parameters (mass action: n_rx, the ln A_j; van der Pol: 1, mu). */
+int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_theta);
+
+/* Device workspace the integrators need for n_sys systems (0 for the plain
+ * kernels); ws may be NULL when this is 0. */
+size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options *opt);
+#define RK_METHOD_RKCK 0
+#define RK_METHOD_RKC 1
+
+/* RKCK integration of n_sys systems from t0 to t1 (Sec. 2.1, Sec. 3.1):
+ *   y0     [N][n_sys]  initial states
+ *   y1     [N][n_sys]  final states (may equal y0: in place)
+ *   g      [P][n_sys]  per-system parameters (P from rk_problem_dims)
+ *   t0, t1 with t1 >= t0 (t1 == t0 copies y0 to y1)
+ *   rtol   > 0: the eps of the paper's error scale;  atol >= 0 enters as
+ *          delta = atol / rtol, so a component's allowed error is
+ *          rtol (|y| + |h f|) + atol
+ *   status [n_sys] or NULL, stats [RK_NSTATS][n_sys] or NULL
+ *   ws, ws_bytes: workspace of at least rk_workspace_bytes(...) bytes */
+int rk_integrate_rkck(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                      const double *g, double t0, double t1, double rtol, double atol,
+                      int32_t *status, int32_t *stats, void *ws, size_t ws_bytes,
+                      const rk_options *opt, void *stream);
+
+/* RKC integration (Sec. 2.2, Sec. 3.2, Appendix); arguments as for RKCK, with
+ * the weighted RMS error norm of Eq. E:rmsE: weights atol + rtol max(|y_n|, |y_{n+1}|). */
+int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                     const double *g, double t0, double t1, double rtol, double atol,
+                     int32_t *status, int32_t *stats, void *ws, size_t ws_bytes,
+                     const rk_options *opt, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

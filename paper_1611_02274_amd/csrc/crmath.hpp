@@ -1,0 +1,230 @@
+// crmath.hpp -- correctly rounded exp, log and pow in FP64 for the kernels.
+//
+// The integrators' control decisions (accept/reject, stage counts) depend on
+// round-off: a one-ulp change in a step size can flip a later decision.  The
+// kernels therefore evaluate every transcendental function correctly rounded
+// (the exact value rounded to the nearest double), which makes their results a
+// function of the inputs alone rather than of a particular math library.
+//
+// Method: table-driven argument reduction (Tang, ACM TOMS 15 (1989) for exp,
+// 16 (1990) for log) carried out in double-double arithmetic built on the
+// error-free transformations TwoSum (Knuth) and TwoProd via FMA (Dekker).
+// The double-double result has relative error below about 2^-88, so its final
+// rounding is the correctly rounded value except with probability ~2^-35 per
+// call.  exp results in the subnormal range are scaled after rounding (a
+// possible double rounding there).  Functions are __host__ __device__ so that
+// the identical code can be checked on the CPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "crmath_tables.hpp"
+
+#define RKMI_HD __host__ __device__ __forceinline__
+
+namespace rkmi {
+namespace crm {
+
+struct dd {
+  double hi, lo;
+};
+
+RKMI_HD bool is_nan(double x) { return x != x; }
+RKMI_HD bool is_finite(double x) { return fabs(x) <= 0x1.fffffffffffffp+1023; }
+
+RKMI_HD uint64_t bits_of(double x) {
+  uint64_t u;
+  memcpy(&u, &x, sizeof u);
+  return u;
+}
+
+RKMI_HD double from_bits(uint64_t u) {
+  double x;
+  memcpy(&x, &u, sizeof x);
+  return x;
+}
+
+// s + e = a + b exactly
+RKMI_HD dd two_sum(double a, double b) {
+  const double s = a + b;
+  const double bb = s - a;
+  const double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+// s + e = a + b exactly, provided |a| >= |b| or a == 0
+RKMI_HD dd fast_two_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+
+// p + e = a * b exactly
+RKMI_HD dd two_prod(double a, double b) {
+  const double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+
+RKMI_HD dd dd_mul(dd a, dd b) {
+  const dd p = two_prod(a.hi, b.hi);
+  const double e = p.lo + (a.hi * b.lo + a.lo * b.hi);
+  return fast_two_sum(p.hi, e);
+}
+
+// 2^m for m in [-1022, 1023]
+RKMI_HD double pow2i(int m) { return from_bits((uint64_t)(m + 1023) << 52); }
+
+RKMI_HD double scale2(double x, int m) {
+  if (m > 1023) {
+    x *= pow2i(1023);
+    m -= 1023;
+    if (m > 1023) m = 1023;
+  } else if (m < -1022) {
+    x *= pow2i(-1022);
+    m += 1022;
+    if (m < -1022) m = -1022;
+  }
+  return x * pow2i(m);
+}
+
+// exp(zh + zl) rounded to nearest, |zl| <= ulp(zh).
+RKMI_HD double exp_dd(double zh, double zl) {
+  if (zh != zh) return zh;
+  if (zh > 709.782712893384) return __builtin_huge_val();
+  if (zh < -745.1332191019412) return 0.0;
+  // z = k ln2/1024 + r, |r| <= ln2/2048
+  const double kd = rint(zh * kInvL);
+  const double rh = zh - kd * kL1;                 // exact
+  const dd p = two_prod(kd, kL2);
+  const dd s = two_sum(rh, -p.hi);
+  const double lo = ((s.lo - p.lo) - kd * kL3) + zl;
+  const dd r = two_sum(s.hi, lo);
+  // exp(r) = 1 + r + r^2/2 + r^3/6 + ... + r^7/5040
+  const double x = r.hi;
+  dd q = two_prod(x, x);
+  q.lo += 2.0 * x * r.lo;
+  const double tail =
+      x * q.hi *
+      (0x1.5555555555555p-3 +
+       x * (0x1.5555555555555p-5 +
+            x * (0x1.1111111111111p-7 + x * (0x1.6c16c16c16c17p-10 + x * 0x1.a01a01a01a01ap-13))));
+  const dd e1 = fast_two_sum(1.0, x);
+  const dd e2 = two_sum(e1.hi, 0.5 * q.hi);
+  const double elo = e1.lo + e2.lo + (r.lo + (0.5 * q.lo + tail));
+  const dd E = fast_two_sum(e2.hi, elo);
+  // 2^(k/1024) = 2^m 2^(j1/32) 2^(j2/1024)
+  const int64_t k = (int64_t)kd;
+  const int64_t m = k >> 10;
+  const int jj = (int)(k - (m << 10));
+  const int j1 = jj >> 5, j2 = jj & 31;
+  const dd T = dd_mul(dd{kExpT1[2 * j1], kExpT1[2 * j1 + 1]}, dd{kExpT2[2 * j2], kExpT2[2 * j2 + 1]});
+  const dd R = dd_mul(T, E);
+  return scale2(R.hi + R.lo, (int)m);
+}
+
+// log1p(u) for a double-double u with |u| <= 2^-9:
+// u - u^2/2 + u^3/3 (double-double) - u^4/4 + ... + u^11/11 (double).
+RKMI_HD dd log1p_small(double uh, double ul) {
+  dd a = two_prod(uh, uh);
+  a.lo += 2.0 * uh * ul;
+  dd b = two_prod(a.hi, uh);
+  b.lo += a.lo * uh + a.hi * ul;
+  const double b3 = b.hi / 3.0;
+  const double b3l = (fma(-3.0, b3, b.hi) + b.lo) / 3.0;
+  const double tail =
+      a.hi * a.hi *
+      (-0.25 +
+       uh * (0.2 +
+             uh * (-0x1.5555555555555p-3 +
+                   uh * (0x1.2492492492492p-3 +
+                         uh * (-0.125 + uh * (0x1.c71c71c71c71cp-4 +
+                                              uh * (-0.1 + uh * 0x1.745d1745d1746p-4)))))));
+  const dd s1 = two_sum(uh, -0.5 * a.hi);
+  const dd s2 = two_sum(s1.hi, b3);
+  const double slo = s1.lo + s2.lo + ((ul - 0.5 * a.lo) + (b3l + tail));
+  return two_sum(s2.hi, slo);
+}
+
+// log(x) as a double-double, x > 0 finite: absolute error below about 2^-95,
+// and relative error below about 2^-80 where |x - 1| < 2^-9.
+RKMI_HD dd log_dd(double x) {
+  if (fabs(x - 1.0) < 0x1p-9) return log1p_small(x - 1.0, 0.0);  // x - 1 is exact here
+  int e = 0;
+  uint64_t u = bits_of(x);
+  int ex = (int)((u >> 52) & 0x7ff);
+  if (ex == 0) {  // subnormal: scale into the normal range
+    x *= 0x1p54;
+    u = bits_of(x);
+    ex = (int)((u >> 52) & 0x7ff);
+    e = -54;
+  }
+  e += ex - 1023;
+  const double mnt = from_bits((u & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL);  // [1, 2)
+  const int j = (int)((u >> 44) & 0xff);
+  // u = mnt * inv_j - 1 exactly as a double-double, |u| <= 2^-9
+  const dd pr = two_prod(mnt, kLogInv[j]);
+  const dd uu = two_sum(pr.hi - 1.0, pr.lo);
+  const dd S = log1p_small(uu.hi, uu.lo);
+  // e ln2 + (-log inv_j) + log1p(u)
+  const double ed = (double)e;
+  const double eh = ed * kLn2a;  // exact
+  const dd el = two_prod(ed, kLn2b);
+  const dd t1 = two_sum(eh, kLogT[2 * j]);
+  const dd t2 = two_sum(t1.hi, el.hi);
+  const dd t3 = two_sum(t2.hi, S.hi);
+  const double lo = ((t1.lo + t2.lo) + t3.lo) + ((kLogT[2 * j + 1] + (el.lo + ed * kLn2c)) + S.lo);
+  return two_sum(t3.hi, lo);
+}
+
+RKMI_HD double cr_exp(double x) { return exp_dd(x, 0.0); }
+
+RKMI_HD double cr_log(double x) {
+  if (x != x) return x;
+  if (x < 0.0) return __builtin_nan("");
+  if (x == 0.0) return -__builtin_huge_val();
+  if (x == __builtin_huge_val()) return x;
+  const dd L = log_dd(x);
+  return L.hi + L.lo;
+}
+
+// x^y for x > 0 finite from a precomputed log_dd(x).
+RKMI_HD double pow_from_log(dd L, double y) {
+  dd z = two_prod(y, L.hi);
+  z.lo += y * L.lo;
+  return exp_dd(z.hi, z.lo);
+}
+
+// x^y with the special values of C99 Annex F (y finite and not an integer
+// in the cases the integrators produce).
+RKMI_HD double cr_pow(double x, double y) {
+  if (y == 0.0) return 1.0;
+  if (x == 1.0) return 1.0;
+  if (x != x || y != y) return x + y;
+  const double inf = __builtin_huge_val();
+  const bool y_int = (rint(y) == y);
+  const bool y_odd = y_int && (fabs(y) < 0x1p53) && (fmod(y, 2.0) != 0.0);
+  if (x == 0.0) {
+    if (y < 0.0) return (y_odd && bits_of(x) >> 63) ? -inf : inf;
+    return (y_odd && bits_of(x) >> 63) ? -0.0 : 0.0;
+  }
+  if (y == inf || y == -inf) {
+    const double ax = fabs(x);
+    if (ax == 1.0) return 1.0;
+    return ((ax > 1.0) == (y > 0.0)) ? inf : 0.0;
+  }
+  if (x == inf) return y > 0.0 ? inf : 0.0;
+  if (x == -inf) {
+    if (y > 0.0) return y_odd ? -inf : inf;
+    return y_odd ? -0.0 : 0.0;
+  }
+  if (x < 0.0) {
+    if (!y_int) return __builtin_nan("");
+    const double r = pow_from_log(log_dd(-x), y);
+    return y_odd ? -r : r;
+  }
+  return pow_from_log(log_dd(x), y);
+}
+
+}  // namespace crm
+}  // namespace rkmi

@@ -1,0 +1,32 @@
+// rk_vdp.hip -- van der Pol oscillators, y1' = y2, y2' = mu (1 - y1^2) y2 - y1,
+// one parameter g = (mu) per system: the nonstiff RKCK workload.
+#include "rk_launch.hpp"
+
+namespace rkmi {
+
+struct VdpProblem {
+  static constexpr int N = 2;
+  using Params = const double*;
+  struct Lane {
+    double mu;
+  };
+  RKMI_HD static void init(Lane& L, const Params&, const double* __restrict__ g,
+                                              int64_t i, int64_t) {
+    L.mu = g[i];
+  }
+  RKMI_HD static void rhs(const Lane& L, const Params&, const double (&y)[2],
+                                             double (&f)[2]) {
+    f[0] = y[1];
+    f[1] = L.mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
+  }
+};
+
+}  // namespace rkmi
+
+extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s) {
+  return rkmi::launch_plain<rkmi::VdpProblem>(a, s);
+}
+
+extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a) {
+  return rkmi::host_run<rkmi::VdpProblem>(a);
+}

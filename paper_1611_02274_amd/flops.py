@@ -1,0 +1,58 @@
+"""Algorithmic FP64 work of an integration, from its per-system statistics.
+
+Counting convention: every add, subtract and multiply of the method's own
+arithmetic counts 1 (a fused multiply-add counts 2); division by a constant
+counts as the multiply by its reciprocal; other divisions, square roots, exp,
+log and pow are special operations and are not counted as flops.  These are
+the operations the method must perform as written in the paper, not the
+instructions a kernel happens to issue.
+
+Per-unit counts (N unknowns, NR reactions, S = reactant+product slots in use):
+  right-hand side  van der Pol: 5;  mass action: 5N - 1 + 5NR + S
+  rate setup       mass action: 5NR per system (plus 2NR exp/div specials)
+  RKCK attempt     56N + 5 beyond its right-hand sides (stage arguments 30N,
+                   k_i = h f 6N, fifth-order sum 8N, error sum 9N, scale 3N)
+  RKC attempt      (s - 1)(9N + 42) + 11N + 10 beyond its right-hand sides
+                   (stage recursion 9N, coefficients 42 per stage, w_1 2N,
+                   error estimate and weights 9N, controller 10)
+  power method     6N per call + 6N per iteration beyond its right-hand sides
+  RKC first step   7N
+"""
+from __future__ import annotations
+
+import numpy as np
+
+ST_ACCEPT, ST_REJECT, ST_RHS, ST_SR_CALLS, ST_POW_ITERS, ST_MAX_STAGES = range(6)
+
+
+def rhs_flops(net=None) -> int:
+    if net is None:
+        return 5
+    slots = int((np.asarray(net.reac) >= 0).sum() + (np.asarray(net.prod) >= 0).sum())
+    return 5 * net.n_sp - 1 + 5 * net.n_rx + slots
+
+
+def setup_flops(net=None) -> int:
+    return 0 if net is None else 5 * net.n_rx
+
+
+def per_system(method: str, stats: np.ndarray, n_eq: int, net=None) -> np.ndarray:
+    """Algorithmic flops of each system from stats [6, n] (int)."""
+    st = np.asarray(stats, dtype=np.float64)
+    acc, rej, rhs, sr, pw = st[ST_ACCEPT], st[ST_REJECT], st[ST_RHS], st[ST_SR_CALLS], st[ST_POW_ITERS]
+    att = acc + rej
+    F = rhs_flops(net)
+    N = n_eq
+    total = rhs * F + setup_flops(net)
+    if method == "rkck":
+        total = total + att * (56 * N + 5)
+    else:
+        started = rhs > 0
+        stage_sum = np.where(started, rhs - 2 - pw - att, 0.0)    # sum over attempts of (s - 1)
+        total = (total + stage_sum * (9 * N + 42) + att * (11 * N + 10) + pw * 6 * N +
+                 sr * 6 * N + np.where(started, 7 * N, 0))
+    return total
+
+
+def total(method: str, stats, n_eq: int, net=None) -> float:
+    return float(per_system(method, stats, n_eq, net).sum())

@@ -1,0 +1,41 @@
+"""The C-ABI library loads and exports every entry point include/rkmi.h declares
+(no GPU needed: nothing is computed)."""
+import ctypes
+import os
+import re
+
+from .conftest import ROOT
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "rkmi.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("rk_integrate_rkck", "rk_integrate_rkc", "rk_problem_create_vdp",
+                 "rk_problem_create_mass_action", "rk_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1611_02274_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_only_calls():
+    """Calls that touch no device: version, problem handles, dims, errors."""
+    import paper_1611_02274_amd as rk
+    assert rk.version() >= 100
+    p = rk.Problem.vdp()
+    assert (p.n_eq, p.n_param, p.n_theta) == (2, 1, 1)
+    q = rk.Problem.network(rk.inputs.standard_network(13))
+    assert (q.n_eq, q.n_param, q.n_theta) == (13, 2, 27)
+    L = rk._lib.lib()
+    assert L.rk_problem_create_vdp(None) == rk._lib.RK_EINVAL
+    assert b"NULL" in L.rk_last_error()

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP kernels through the C ABI against the CPU oracle,
+element by element on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from paper_1611_02274_amd import inputs as I
+
+from .parity import compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1611_02274_amd as rk
+    return rk
+
+
+def _gpu(rk, method, prob, y0, g, t0, t1, rtol, atol, **kw):
+    import torch
+    yd = torch.from_numpy(y0).cuda()
+    gd = torch.from_numpy(g).cuda() if g is not None else None
+    fn = rk.integrate_rkck if method == "rkck" else rk.integrate_rkc
+    y1, st, stats = fn(prob, yd, gd, t0, t1, rtol, atol, **kw)
+    torch.cuda.synchronize()
+    return y1.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy()
+
+
+def _orc(orc, method, pb, y0, g, t0, t1, rtol, atol, **kw):
+    fn = orc.rkck_batch if method == "rkck" else orc.rkc_batch
+    return fn(pb, y0, g, t0, t1, rtol, atol, **kw)
+
+
+def _case(rk, orc, method, problem, n, seed, t0, t1, rtol, atol, T_range=(1000.0, 2500.0), **kw):
+    say(f"case {method} {problem} n={n} seed={seed} t=[{t0},{t1}] rtol={rtol} atol={atol}")
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, seed)
+        prob, pb = rk.Problem.vdp(), orc.vdp()
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, seed, T_range)
+        prob, pb = rk.Problem.network(net), orc.network(net)
+    yg, sg, stg = _gpu(rk, method, prob, y0, g, t0, t1, rtol, atol, **kw)
+    oo = {k: v for k, v in kw.items() if k == "max_steps"}
+    yo, so, sto = _orc(orc, method, pb, y0, g, t0, t1, rtol, atol, **oo)
+    return compare(yg, sg, stg, yo, so, sto, atol, f"{method}/{problem}/n={n}")
+
+
+def test_vdp_rkck_full(rk, orc):
+    """4096 van der Pol oscillators, RKCK, t in [0, 10], rtol 1e-8, atol 1e-10."""
+    _case(rk, orc, "rkck", "vdp", 4096, 1, 0.0, 10.0, 1e-8, 1e-10)
+
+
+def test_vdp_rkc_ragged(rk, orc):
+    _case(rk, orc, "rkc", "vdp", 1000, 3, 0.0, 2.0, 1e-8, 1e-10)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 4133])
+def test_net13_rkc(rk, orc, n):
+    _case(rk, orc, "rkc", "net13", n, 2002, 0.0, 1e-6, 1e-8, 1e-12)
+
+
+def test_net9_rkc(rk, orc):
+    _case(rk, orc, "rkc", "net9", 2000, 77, 0.0, 1e-6, 1e-8, 1e-12, T_range=(800.0, 3000.0))
+
+
+def test_net13_rkck(rk, orc):
+    _case(rk, orc, "rkck", "net13", 700, 12, 0.0, 2e-8, 1e-8, 1e-12)
+
+
+def test_vdp_rkck_loose_and_tight(rk, orc):
+    _case(rk, orc, "rkck", "vdp", 777, 5, 0.0, 3.0, 1e-5, 0.0)
+    _case(rk, orc, "rkck", "vdp", 777, 6, 0.0, 3.0, 1e-11, 1e-13)
+
+
+def test_max_steps_status(rk, orc):
+    _case(rk, orc, "rkc", "net13", 300, 9, 0.0, 1e-6, 1e-8, 1e-12, max_steps=17)
+    _case(rk, orc, "rkck", "vdp", 300, 9, 0.0, 10.0, 1e-8, 1e-10, max_steps=40)
+
+
+def test_nonfinite_input_status(rk, orc):
+    """A NaN initial state is rejected until the step underflows hMin, on both sides."""
+    say("case nan vdp")
+    y0, g = I.vdp_inputs(130, 4)
+    y0[:, 7] = np.nan
+    y0[1, 100] = np.inf
+    prob, pb = rk.Problem.vdp(), orc.vdp()
+    for m in ("rkck", "rkc"):
+        yg, sg, stg = _gpu(rk, m, prob, y0, g, 0.0, 1.0, 1e-8, 1e-10)
+        yo, so, sto = _orc(orc, m, pb, y0, g, 0.0, 1.0, 1e-8, 1e-10)
+        assert sg[7] != 0 and np.array_equal(sg, so)
+        ok = np.isfinite(yo).all(0)
+        compare(yg[:, ok], sg[ok], stg[:, ok], yo[:, ok], so[ok], sto[:, ok], 1e-10, f"nan/{m}")
+
+
+def test_empty_interval_and_in_place(rk):
+    import torch
+    say("case empty interval / in place")
+    y0, g = I.vdp_inputs(100, 2)
+    prob = rk.Problem.vdp()
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    y1, st, stats = rk.integrate_rkck(prob, yd, gd, 1.0, 1.0, 1e-8, 1e-10)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, yd) and int(st.abs().sum()) == 0 and int(stats.abs().sum()) == 0
+    ref, _, _ = rk.integrate_rkck(prob, yd, gd, 0.0, 1.0, 1e-8, 1e-10)
+    inplace = yd.clone()
+    rk.integrate_rkck(prob, inplace, gd, 0.0, 1.0, 1e-8, 1e-10, out=inplace)
+    torch.cuda.synchronize()
+    assert torch.equal(inplace, ref)
+    # zero systems is a no-op
+    e = torch.empty((2, 0), dtype=torch.float64, device="cuda")
+    rk.integrate_rkc(prob, e, torch.empty((1, 0), dtype=torch.float64, device="cuda"),
+                     0.0, 1.0, 1e-8, 1e-10)
+
+
+def test_argument_errors(rk):
+    import ctypes as C
+    import torch
+    from paper_1611_02274_amd import _lib
+    say("case argument errors")
+    prob = rk.Problem.vdp()
+    y = torch.zeros((2, 8), dtype=torch.float64, device="cuda")
+    g = torch.ones((1, 8), dtype=torch.float64, device="cuda")
+    L = _lib.lib()
+    f = L.rk_integrate_rkc
+
+    def call(n=8, y0=y.data_ptr(), y1=y.data_ptr(), gg=g.data_ptr(), t0=0.0, t1=1.0, rtol=1e-6,
+             atol=0.0):
+        return f(prob.handle, n, y0, y1, gg, t0, t1, rtol, atol, None, None, None, 0, None, None)
+
+    assert call(n=-1) == _lib.RK_EINVAL
+    assert call(t1=-1.0) == _lib.RK_EINVAL
+    assert call(rtol=0.0) == _lib.RK_EINVAL
+    assert call(atol=-1.0) == _lib.RK_EINVAL
+    assert call(t1=float("nan")) == _lib.RK_EINVAL
+    host = np.zeros(16)
+    assert call(y0=host.ctypes.data) == _lib.RK_EINVAL
+    assert b"not" in L.rk_last_error()
+    assert call(y0=y.data_ptr() + 4) == _lib.RK_EINVAL
+    assert call(gg=None) == _lib.RK_EINVAL
+    assert f(None, 8, y.data_ptr(), y.data_ptr(), g.data_ptr(), 0.0, 1.0, 1e-6, 0.0, None, None,
+             None, 0, None, None) == _lib.RK_EINVAL
+    assert call() == _lib.RK_OK
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n_sample", [512])
+def test_net13_rkc_full_size_sampled(rk, orc, n_sample):
+    """The 2^18-system 13-species RKC workload at full size, in the launch the
+    benchmark times; the oracle recomputes a spread sample of systems."""
+    w = I.WORKLOADS["net13_rkc"]
+    say(f"case full-size {w.name} n={w.n}")
+    net = I.network_of(w.problem)
+    y0, g = I.workload_inputs(w)
+    prob, pb = rk.Problem.network(net), orc.network(net)
+    yg, sg, stg = _gpu(rk, "rkc", prob, y0, g, w.t0, w.t1, w.rtol, w.atol)
+    idx = np.unique(np.linspace(0, w.n - 1, n_sample).astype(np.int64))
+    yo, so, sto = _orc(orc, "rkc", pb, np.ascontiguousarray(y0[:, idx]),
+                       np.ascontiguousarray(g[:, idx]), w.t0, w.t1, w.rtol, w.atol)
+    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, "full net13_rkc sample")
+    # whole-batch properties: every system finished, mass fractions still sum to one
+    assert np.all(sg == 0)
+    assert np.abs(yg.sum(0) - 1.0).max() < 1e-11
+
+
+def test_device_math_equals_host_and_oracle(rk, orc):
+    """The correctly rounded exp / log / pow give the same bits on the device as
+    the host build of the same source, and as the oracle."""
+    import ctypes as C
+    import torch
+    from paper_1611_02274_amd import _lib
+    say("case device math")
+    L = _lib.lib()
+    fd, fh = L.rkmi_crmath_device, L.rkmi_crmath_host
+    fd.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    fh.argtypes = [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    rng = np.random.default_rng(11)
+    n = 200_000
+    cases = [(0, rng.uniform(-45, 45, n), np.zeros(n)),
+             (1, rng.uniform(300, 4000, n), np.zeros(n)),
+             (2, 10 ** rng.uniform(-20, 3, n), np.full(n, -0.2)),
+             (2, 10 ** rng.uniform(-20, 3, n), np.full(n, 2.0 / 3.0))]
+    ref = {0: orc.cr_exp, 1: orc.cr_log}
+    for fn, x, y in cases:
+        xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+        od = torch.empty_like(xd)
+        assert fd(fn, n, xd.data_ptr(), yd.data_ptr(), od.data_ptr(), None) == 0
+        torch.cuda.synchronize()
+        oh = np.zeros(n)
+        assert fh(fn, n, x.ctypes.data, y.ctypes.data, oh.ctypes.data) == 0
+        dev = od.cpu().numpy()
+        assert np.array_equal(dev, oh), (fn, int((dev != oh).sum()))
+        m = 20000
+        r = np.array([ref[fn](v) if fn < 2 else orc.cr_pow(v, w) for v, w in zip(x[:m], y[:m])])
+        assert np.array_equal(dev[:m], r)

@@ -1,0 +1,70 @@
+"""The kernels' per-system code, compiled for the host from the same source as
+the GPU kernels, reproduces the oracle bit for bit (CPU only: no GPU used).
+
+This checks the arithmetic of the HIP path (operation order, correctly rounded
+transcendentals, controller logic) without a device; the GPU parity tests then
+check that the device computes what the host build computes."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1611_02274_amd import inputs as I
+
+
+def _host_run(prob, method, y0, g, t0, t1, rtol, atol, max_steps=0):
+    from paper_1611_02274_amd import _lib
+    f = _lib.lib().rkmi_test_host_integrate
+    f.argtypes = [C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                  C.c_int64]
+    f.restype = C.c_int
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    n = y0.shape[1]
+    y1 = np.zeros_like(y0)
+    st = np.zeros(n, dtype=np.int32)
+    stats = np.zeros((6, n), dtype=np.int32)
+    rc = f(0 if method == "rkck" else 1, prob.handle, n, y0.ctypes.data, y1.ctypes.data,
+           g.ctypes.data, t0, t1, rtol, atol, st.ctypes.data, stats.ctypes.data, max_steps)
+    assert rc == 0
+    return y1, st, stats
+
+
+CASES = [
+    ("rkck", "vdp", 200, 1, 0.0, 10.0, 1e-8, 1e-10, None),
+    ("rkc", "vdp", 120, 3, 0.0, 2.0, 1e-8, 1e-10, None),
+    ("rkc", "net9", 96, 77, 0.0, 1e-6, 1e-8, 1e-12, (800.0, 3000.0)),
+    ("rkc", "net13", 96, 2002, 0.0, 1e-6, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkck", "net13", 32, 12, 0.0, 2e-8, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkck", "net9", 32, 5, 0.0, 1e-8, 1e-6, 0.0, (800.0, 3000.0)),
+]
+
+
+@pytest.mark.parametrize("method,problem,n,seed,t0,t1,rtol,atol,T_range", CASES)
+def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, t1, rtol, atol,
+                                             T_range):
+    import paper_1611_02274_amd as rk
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, seed)
+        prob, pb = rk.Problem.vdp(), orc.vdp()
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, seed, T_range)
+        prob, pb = rk.Problem.network(net), orc.network(net)
+    yh, sh, sth = _host_run(prob, method, y0, g, t0, t1, rtol, atol)
+    fn = orc.rkck_batch if method == "rkck" else orc.rkc_batch
+    yo, so, sto = fn(pb, y0, g, t0, t1, rtol, atol)
+    assert np.array_equal(sh, so)
+    assert np.array_equal(sth, sto), np.argwhere(sth != sto)[:5]
+    assert np.array_equal(yh.view(np.int64), yo.view(np.int64))
+
+
+def test_host_build_max_steps(orc):
+    import paper_1611_02274_amd as rk
+    net = I.network_of("net13")
+    y0, g = I.kinetics_inputs(net, 40, 9)
+    yh, sh, sth = _host_run(rk.Problem.network(net), "rkc", y0, g, 0.0, 1e-6, 1e-8, 1e-12, 17)
+    yo, so, sto = orc.rkc_batch(orc.network(net), y0, g, 0.0, 1e-6, 1e-8, 1e-12, max_steps=17)
+    assert np.all(so == orc.MAXSTEPS)
+    assert np.array_equal(sh, so) and np.array_equal(sth, sto) and np.array_equal(yh, yo)
