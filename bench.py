@@ -25,6 +25,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summaries
+    (FETCH_SIZE, WRITE_SIZE scaled by a 1 GiB copy), or None when none matches
+    this workload and the current kernel sources."""
+    import glob
+
+    from paper_1611_02274_amd.build import kernel_source_digest
+    digest = kernel_source_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                parts = line.strip().split(":", 1)
+                if len(parts) == 2 and parts[0].startswith(("traffic_", "kernel_source")):
+                    kv[parts[0].strip()] = parts[1].strip()
+        if kv.get("traffic_workload") == workload and kv.get("kernel_source_sha1") == digest:
+            return float(kv["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
+
+
 def cpu_baseline(w, net, y0, g, target_s: float):
     """The oracle (serial per system, OpenMP across systems) on a bounded sample."""
     import numpy as np
@@ -57,7 +77,19 @@ def main():
     ap.add_argument("--workload", default="net13_rkc")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a device-to-device copy of 1 GiB, three times (the known "
+                         "traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the systems are "
               "independent, so a multi-GPU run is one shard per GPU with no exchange",
@@ -109,6 +141,7 @@ def main():
     status_h = status.cpu().numpy()
     flops = FL.total(w.method, st_h, prob.n_eq, net)
     achieved = flops / (kern_ms * 1e-3) / 1e12
+    traffic, traffic_src = measured_traffic(w.name)
     value = w.n * args.steps / elapsed
     res = {
         "metric": METRIC,
@@ -133,7 +166,8 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+            "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
             "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops,
         },
     }

@@ -44,6 +44,20 @@ def sources():
     return hand + gen
 
 
+def kernel_source_digest() -> str:
+    """SHA-1 over every kernel source and the compile flags: identifies the
+    kernels a measurement was taken on."""
+    import hashlib
+    h = hashlib.sha1(" ".join(CXXFLAGS).encode())
+    for d in (CSRC, GEN):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".hpp", ".cpp")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode())
+                    h.update(fh.read())
+    return h.hexdigest()
+
+
 def _compile(src: str, resource_usage: bool) -> tuple[str, str]:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
     if src.endswith(".cpp"):   # host-only C++ (no device code)
