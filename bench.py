@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--workload", default="net13_rkc")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "plain", "persistent"])
+    ap.add_argument("--refill", type=int, default=0,
+                    help="persistent schedule: idle lanes that trigger a refill (0: default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device-to-device copy of 1 GiB, three times (the known "
                          "traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -115,9 +118,11 @@ def main():
     status = torch.empty(w.n, dtype=torch.int32, device=dev)
     stats = torch.empty((rk.RK_NSTATS, w.n), dtype=torch.int32, device=dev)
     fn = rk.integrate_rkck if w.method == "rkck" else rk.integrate_rkc
+    sched = {"auto": 0, "plain": 1, "persistent": 2}[args.schedule]
 
     def step():
-        fn(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, out=out, status=status, stats=stats)
+        fn(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, out=out, status=status, stats=stats,
+           schedule=sched, refill=args.refill)
 
     for k in range(args.warmup):
         step()
@@ -159,7 +164,8 @@ def main():
         "config": {
             "workload": w.name, "method": w.method, "problem": w.problem, "n_systems": w.n,
             "t0": w.t0, "t1": w.t1, "rtol": w.rtol, "atol": w.atol,
-            "kernel": "plain (one system per lane)",
+            "schedule": "persistent (lanes refilled from a device queue)"
+                        if args.schedule != "plain" else "plain (one system per lane)",
             "systems_ok": int((status_h == 0).sum()),
             "mean_accepted_steps": float(st_h[0].mean()),
             "mean_rhs_evals": float(st_h[2].mean()),

@@ -92,8 +92,11 @@ typedef struct {
   int64_t max_steps;    /* attempts per system before RK_SYS_MAXSTEPS; <= 0: 10^7 */
   int32_t sr_period;    /* RKC: spectral radius every this many accepted steps; <= 0: 25 */
   int32_t sr_itmax;     /* RKC: power-method iteration limit; <= 0: 50 */
-  int32_t schedule;     /* 0: automatic; 1: plain one-lane-per-system kernel */
-  int32_t reserved[7];  /* set to 0 */
+  int32_t schedule;     /* RK_SCHED_*: 0 automatic (persistent when the workspace is large
+                           enough, else plain), 1 plain, 2 persistent (needs workspace) */
+  int32_t refill;       /* persistent schedule: a wave takes new systems once at least this
+                           many of its 64 lanes are idle (1..64; <= 0: tuned default) */
+  int32_t reserved[6];  /* set to 0 */
 } rk_options;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -120,8 +123,17 @@ void rk_problem_destroy(rk_problem p);
  * parameters (mass action: n_rx, the ln A_j; van der Pol: 1, mu). */
 int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_theta);
 
-/* Device workspace the integrators need for n_sys systems (0 for the plain
- * kernels); ws may be NULL when this is 0. */
+/* Schedules.  Plain: one lane per system, system i on global lane i (the
+ * paper's intDriver, Sec. 3).  Persistent: a machine-sized grid whose lanes take
+ * the next system from a device-side queue as soon as theirs is finished. */
+#define RK_SCHED_AUTO 0
+#define RK_SCHED_PLAIN 1
+#define RK_SCHED_PERSISTENT 2
+
+/* Device workspace (bytes) the integrators use for n_sys systems under *opt
+ * (NULL = defaults): 0 for the plain schedule, a small queue block for the
+ * persistent one.  The caller allocates it; it must not be shared by calls
+ * that may run concurrently. */
 size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options *opt);
 #define RK_METHOD_RKCK 0
 #define RK_METHOD_RKC 1

@@ -69,14 +69,15 @@ class Problem:
             _lib._lib.rk_problem_destroy(h)
 
 
-def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None):
-    if max_steps is None and sr_period is None and sr_itmax is None and schedule is None:
+def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refill=None):
+    if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill)):
         return None
     o = _lib.Options()
     o.max_steps = int(max_steps or 0)
     o.sr_period = int(sr_period or 0)
     o.sr_itmax = int(sr_itmax or 0)
     o.schedule = int(schedule or 0)
+    o.refill = int(refill or 0)
     return o
 
 
@@ -117,14 +118,17 @@ def _integrate(method, problem: Problem, y0, g, t0, t1, rtol, atol, out=None, st
         stats = torch.empty((RK_NSTATS, n), dtype=torch.int32, device=dev)
     _check_tensor(stats, "stats", RK_NSTATS, n, torch.int32)
     opt = _options(**opts)
+    optp = C.byref(opt) if opt is not None else None
+    L = _lib.lib()
     with torch.cuda.device(dev):
         s = stream if stream is not None else torch.cuda.current_stream(dev)
-        fn = (_lib.lib().rk_integrate_rkck if method == RK_METHOD_RKCK
-              else _lib.lib().rk_integrate_rkc)
+        nws = L.rk_workspace_bytes(problem.handle, method, n, optp)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev) if nws else None
+        fn = L.rk_integrate_rkck if method == RK_METHOD_RKCK else L.rk_integrate_rkc
         _lib.check(fn(problem.handle, n, y0.data_ptr(), out.data_ptr(),
                       g.data_ptr() if problem.n_param else None, float(t0), float(t1),
-                      float(rtol), float(atol), status.data_ptr(), stats.data_ptr(), None, 0,
-                      C.byref(opt) if opt is not None else None, s.cuda_stream))
+                      float(rtol), float(atol), status.data_ptr(), stats.data_ptr(),
+                      ws.data_ptr() if ws is not None else None, nws, optp, s.cuda_stream))
     return out, status, stats
 
 

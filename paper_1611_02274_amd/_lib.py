@@ -33,7 +33,7 @@ class MechDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("sr_period", C.c_int32), ("sr_itmax", C.c_int32),
-                ("schedule", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("schedule", C.c_int32), ("refill", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class RKError(RuntimeError):

@@ -195,6 +195,18 @@ RKMI_HD double pow_from_log(dd L, double y) {
   return exp_dd(z.hi, z.lo);
 }
 
+// log_dd of a finite x >= 0, for several powers of the same x (x = 0 gives an
+// unused value).
+RKMI_HD dd log_of_nonneg(double x) { return x > 0.0 ? log_dd(x) : dd{0.0, 0.0}; }
+
+// x^y for finite x >= 0 and finite y, given L = log_of_nonneg(x): the same
+// value as cr_pow(x, y).
+RKMI_HD double pow_from_log_nonneg(double x, dd L, double y) {
+  if (y == 0.0 || x == 1.0) return 1.0;
+  if (x == 0.0) return y < 0.0 ? __builtin_huge_val() : 0.0;
+  return pow_from_log(L, y);
+}
+
 // x^y with the special values of C99 Annex F (y finite and not an integer
 // in the cases the integrators produce).
 RKMI_HD double cr_pow(double x, double y) {

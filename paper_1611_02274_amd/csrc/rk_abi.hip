@@ -132,7 +132,9 @@ void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, dou
   c.mmax = mmax < 2 ? 2 : mmax;
   c.sr_period = (opt && opt->sr_period > 0) ? opt->sr_period : 25;
   c.sr_itmax = (opt && opt->sr_itmax > 0) ? opt->sr_itmax : 50;
-  c.pad = 0;
+  c.refill = (opt && opt->refill > 0) ? (opt->refill > rkmi::kLdsStride ? rkmi::kLdsStride
+                                                                        : opt->refill)
+                                      : rkmi::kDefaultRefill;
   a.status = status;
   a.stats = stats;
   a.ws = ws;
@@ -150,10 +152,13 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(RK_EINVAL, "rtol must be positive");
   if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(RK_EINVAL, "atol must be >= 0");
   if (opt) {
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 6; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
-    if (opt->schedule < 0 || opt->schedule > 1)
+    if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedPersistent)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
+    if (opt->schedule == rkmi::kSchedPersistent && (!ws || ws_bytes < rkmi::kQueueBytes))
+      return fail(RK_EWORKSPACE, "the persistent schedule needs %zu bytes of workspace",
+                  (size_t)rkmi::kQueueBytes);
   }
   if (n == 0) return RK_OK;
   int rc;
@@ -162,8 +167,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if ((rc = check_device_ptr(g, 8, "g", p->n_param == 0))) return rc;
   if ((rc = check_device_ptr(status, 4, "status", true))) return rc;
   if ((rc = check_device_ptr(stats, 4, "stats", true))) return rc;
-  (void)ws;
-  (void)ws_bytes;
+  if ((rc = check_device_ptr(ws, 8, "ws", true))) return rc;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (t1 == t0) {
     // nothing to integrate: copy the state, zero status and statistics (a
@@ -295,9 +299,8 @@ int rk_problem_dims(rk_problem p, int32_t* n_eq, int32_t* n_param, int32_t* n_th
 size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options* opt) {
   (void)p;
   (void)method;
-  (void)n_sys;
-  (void)opt;
-  return 0;
+  if (n_sys <= 0 || (opt && opt->schedule == rkmi::kSchedPlain)) return 0;
+  return rkmi::kQueueBytes;
 }
 
 int rk_integrate_rkck(rk_problem p, int64_t n_sys, const double* y0, double* y1, const double* g,

@@ -1,4 +1,5 @@
-// rk_device.hpp -- device-side RKCK / RKC drivers for one ODE system per lane.
+// rk_device.hpp -- RKCK / RKC drivers for one ODE system per lane, and the
+// kernels that schedule them.
 //
 // Method: Niemeyer & Sung (2014).  RKCK: Table 1, Sec. 2.1 stage equations,
 // error estimate and step-size rule, Sec. 3.1 driver.  RKC: Sec. 2.2 stage
@@ -12,13 +13,18 @@
 //     v = f(t0, y0)); a non-finite RKC error is a rejection with h *= P1;
 //     rejection step 0.8 h / err^(1/3) without a floor;
 //   * guards: h below hMin after a rejection, a non-finite accepted state or
-//     max_steps attempts end the system with a status code.
+//     max_steps attempts end the system with a status code;
+//   * exp, log and pow are correctly rounded (crmath.hpp).
+// Every expression is written in the order of the reference evaluation and the
+// library is built without contraction, so results are reproducible bit for bit.
 //
 // A problem type Prob supplies
-//   static constexpr int N;              unknowns
-//   struct Lane;                         per-system constants (registers)
-//   using Params;                        uniform data passed by value
-//   static void init(Lane&, const Params&, const double* g, int64_t i, int64_t n);
+//   static constexpr int N;             unknowns
+//   static constexpr int kLaneDoubles;  per-system constants kept in LDS
+//   using Params;                       uniform data passed by value
+//   struct Lane;                        per-system constants kept in registers
+//   static void init(Lane&, const Params&, const double* g, int64_t i, int64_t n,
+//                    double* slot);     slot[j * kLdsStride], j < kLaneDoubles
 //   static void rhs(const Lane&, const Params&, const double (&y)[N], double (&f)[N]);
 // Every right-hand side here is autonomous, so stage times are not formed.
 #pragma once
@@ -38,6 +44,10 @@ constexpr double kPShrink = -0.25;
 constexpr double kErrCon = 1.89e-4;
 constexpr double kP1 = 0.1;
 constexpr double kRkckHmin = 1.0e-20;
+
+// Lanes per workgroup of every integration kernel (one wave64), which is also
+// the stride of the per-lane columns in LDS.
+constexpr int kLdsStride = 64;
 
 enum : int32_t { kSysOk = 0, kSysNonFinite = 1, kSysHmin = 2, kSysMaxSteps = 3 };
 enum : int { kStAccept = 0, kStReject, kStRhs, kStSrCalls, kStPowIters, kStMaxStages, kNStats };
@@ -75,11 +85,9 @@ constexpr double e1 = -277.0 / 64512.0, e3 = 6925.0 / 370944.0, e4 = -6925.0 / 2
 // One trial step: k_1 = h F, k_i = h f(y + sum_j b_ij k_j); returns the
 // fifth-order solution and the error estimate sum_i (c_i - c*_i) k_i.
 template <class Prob>
-RKMI_HD void rkck_trial(const typename Prob::Lane& L,
-                                           const typename Prob::Params& prm,
-                                           const double (&y)[Prob::N], const double (&F)[Prob::N],
-                                           double h, double (&yt)[Prob::N],
-                                           double (&ye)[Prob::N]) {
+RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                        const double (&y)[Prob::N], const double (&F)[Prob::N], double h,
+                        double (&yt)[Prob::N], double (&ye)[Prob::N]) {
   constexpr int N = Prob::N;
   double k1[N], k2[N], k3[N], k4[N], k5[N], z[N], f[N];
 #pragma unroll
@@ -121,71 +129,90 @@ RKMI_HD void rkck_trial(const typename Prob::Lane& L,
   }
 }
 
-// Per-lane RKCK integration of one system from t0 to t1 (in place on y).
+// Integration state of one system under RKCK.
+template <int N>
+struct RkckState {
+  double y[N], F[N];
+  double t, h;
+  int64_t attempts;
+  int32_t n_acc, n_rej, n_rhs, status;
+  bool fvalid;
+};
+
 template <class Prob>
-__host__ __device__ int32_t rkck_integrate(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                                  const Ctl& c, double (&y)[Prob::N], int32_t (&st)[kNStats]) {
+RKMI_HD void rkck_begin(RkckState<Prob::N>& S, const Ctl& c) {
+  S.t = c.t0;
+  S.h = 0.5 * c.hmax;
+  S.fvalid = false;
+  S.status = kSysOk;
+  S.attempts = 0;
+  S.n_acc = S.n_rej = S.n_rhs = 0;
+}
+
+RKMI_HD bool rkck_running(const RkckState<1>&, const Ctl&) { return true; }
+
+// One attempted step of the RKCK driver (Sec. 3.1); returns true while the
+// system still has to step (t < t1 and no failure).
+template <class Prob>
+RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                          const Ctl& c, RkckState<Prob::N>& S) {
   constexpr int N = Prob::N;
-  double F[N], yt[N], ye[N];
-  double t = c.t0;
-  double h = 0.5 * c.hmax;
-  bool fvalid = false;
-  int32_t status = kSysOk;
-  int64_t attempts = 0;
-  int32_t n_acc = 0, n_rej = 0, n_rhs = 0;
-  while (t < c.t1) {
-    if (attempts >= c.max_steps) {
-      status = kSysMaxSteps;
-      break;
-    }
-    h = fmin(c.t1 - t, h);
-    if (!fvalid) {
-      Prob::rhs(L, prm, y, F);
-      ++n_rhs;
-      fvalid = true;
-    }
-    rkck_trial<Prob>(L, prm, y, F, h, yt, ye);
-    n_rhs += 5;
-    ++attempts;
-    // scaled error max_i |yerr_i / (|y_i| + |h F_i| + delta)| / rtol
-    double err = 0.0;
-    bool nan_flag = false;
+  if (S.attempts >= c.max_steps) {
+    S.status = kSysMaxSteps;
+    return false;
+  }
+  S.h = fmin(c.t1 - S.t, S.h);
+  if (!S.fvalid) {
+    Prob::rhs(L, prm, S.y, S.F);
+    ++S.n_rhs;
+    S.fvalid = true;
+  }
+  double yt[N], ye[N];
+  rkck_trial<Prob>(L, prm, S.y, S.F, S.h, yt, ye);
+  S.n_rhs += 5;
+  ++S.attempts;
+  // scaled error max_i |yerr_i / (|y_i| + |h F_i| + delta)| / rtol
+  double err = 0.0;
+  bool nan_flag = false;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      nan_flag = nan_flag || crm::is_nan(ye[i]);
-      err = fmax(err, fabs(ye[i] / (fabs(y[i]) + fabs(h * F[i]) + c.delta)));
+  for (int i = 0; i < N; ++i) {
+    nan_flag = nan_flag || crm::is_nan(ye[i]);
+    err = fmax(err, fabs(ye[i] / (fabs(S.y[i]) + fabs(S.h * S.F[i]) + c.delta)));
+  }
+  err = err / c.rtol;
+  if ((err > 1.0) || crm::is_nan(err) || nan_flag) {
+    ++S.n_rej;
+    if (crm::is_nan(err) || nan_flag)
+      S.h = S.h * kP1;
+    else
+      S.h = fmax(kSafety * S.h * crm::cr_pow(err, kPShrink), kP1 * S.h);
+    if (!(S.h >= kRkckHmin)) {
+      S.status = kSysHmin;
+      return false;
     }
-    err = err / c.rtol;
-    if ((err > 1.0) || crm::is_nan(err) || nan_flag) {
-      ++n_rej;
-      if (crm::is_nan(err) || nan_flag)
-        h = h * kP1;
-      else
-        h = fmax(kSafety * h * crm::cr_pow(err, kPShrink), kP1 * h);
-      if (!(h >= kRkckHmin)) {
-        status = kSysHmin;
-        break;
-      }
-    } else {
-      t += h;
-      double hn = (err > kErrCon) ? kSafety * h * crm::cr_pow(err, kPGrow) : h * 5.0;
-      h = fmax(kRkckHmin, fmin(c.hmax, hn));
-      copy(y, yt);
-      ++n_acc;
-      fvalid = false;
-      if (!all_finite(y)) {
-        status = kSysNonFinite;
-        break;
-      }
+  } else {
+    S.t += S.h;
+    const double hn = (err > kErrCon) ? kSafety * S.h * crm::cr_pow(err, kPGrow) : S.h * 5.0;
+    S.h = fmax(kRkckHmin, fmin(c.hmax, hn));
+    copy(S.y, yt);
+    ++S.n_acc;
+    S.fvalid = false;
+    if (!all_finite(S.y)) {
+      S.status = kSysNonFinite;
+      return false;
     }
   }
-  st[kStAccept] = n_acc;
-  st[kStReject] = n_rej;
-  st[kStRhs] = n_rhs;
+  return S.t < c.t1;
+}
+
+template <int N>
+RKMI_HD void rkck_stats(const RkckState<N>& S, int32_t (&st)[kNStats]) {
+  st[kStAccept] = S.n_acc;
+  st[kStReject] = S.n_rej;
+  st[kStRhs] = S.n_rhs;
   st[kStSrCalls] = 0;
   st[kStPowIters] = 0;
   st[kStMaxStages] = 6;
-  return status;
 }
 
 // =========================================================================
@@ -199,9 +226,9 @@ RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
   w0 = 1.0 + kKappa / ((double)s * (double)s);
   double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
   for (int j = 2; j <= s; ++j) {
-    double Tj = 2.0 * w0 * Tm1 - Tm2;
-    double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-    double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
+    const double Tj = 2.0 * w0 * Tm1 - Tm2;
+    const double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
+    const double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
     Tm2 = Tm1; Tm1 = Tj;
     Dm2 = Dm1; Dm1 = Dj;
     Em2 = Em1; Em1 = Ej;
@@ -212,49 +239,45 @@ RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
 // One RKC step of s stages from (y_n, F_n = f(y_n)) into y (Eqs. E:rkc0 - E:rkcs);
 // the coefficients b_j, mu_j, nu_j, mut_j, gt_j are formed stage by stage.
 template <class Prob>
-RKMI_HD void rkc_step(const typename Prob::Lane& L,
-                                         const typename Prob::Params& prm,
-                                         const double (&yn)[Prob::N], const double (&Fn)[Prob::N],
-                                         double h, int s, double (&y)[Prob::N]) {
+RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                      const double (&yn)[Prob::N], const double (&Fn)[Prob::N], double h, int s,
+                      double (&y)[Prob::N]) {
   constexpr int N = Prob::N;
   double w0, w1;
   rkc_omegas(s, w0, w1);
-  // j = 2 values of the recurrence: T_2 = 2 w0^2 - 1, T_2' = 4 w0, T_2'' = 4
   double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
   double b2;
   {
-    double T2 = 2.0 * w0 * Tm1 - Tm2;
-    double D2 = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-    double E2 = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-    (void)T2;
+    const double D2 = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
+    const double E2 = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
     b2 = E2 / (D2 * D2);
   }
   double bjm1 = b2, bjm2 = b2;           // b_1 = b_0 = b_2
   double ajm1 = 1.0 - bjm1 * w0;         // a_1 = 1 - b_1 T_1
-  double wjm1[N], wjm2[N], f[N];
+  double wjm2[N], f[N];
   const double mh1 = (bjm1 * w1) * h;    // mut_1 h
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     wjm2[i] = yn[i];
-    wjm1[i] = yn[i] + mh1 * Fn[i];
+    y[i] = yn[i] + mh1 * Fn[i];          // y holds w_{j-1}
   }
   for (int j = 2; j <= s; ++j) {
-    double Tj = 2.0 * w0 * Tm1 - Tm2;
-    double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-    double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-    double bj = Ej / (Dj * Dj);
-    double mu = 2.0 * bj * w0 / bjm1;
-    double nu = -bj / bjm2;
-    double mut = 2.0 * bj * w1 / bjm1;
-    double gt = -ajm1 * mut;
-    double c0 = 1.0 - mu - nu;
-    double mh = mut * h, gh = gt * h;
-    Prob::rhs(L, prm, wjm1, f);
+    const double Tj = 2.0 * w0 * Tm1 - Tm2;
+    const double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
+    const double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
+    const double bj = Ej / (Dj * Dj);
+    const double mu = 2.0 * bj * w0 / bjm1;
+    const double nu = -bj / bjm2;
+    const double mut = 2.0 * bj * w1 / bjm1;
+    const double gt = -ajm1 * mut;
+    const double c0 = 1.0 - mu - nu;
+    const double mh = mut * h, gh = gt * h;
+    Prob::rhs(L, prm, y, f);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      double wj = c0 * yn[i] + mu * wjm1[i] + nu * wjm2[i] + mh * f[i] + gh * Fn[i];
-      wjm2[i] = wjm1[i];
-      wjm1[i] = wj;
+      const double wj = c0 * yn[i] + mu * y[i] + nu * wjm2[i] + mh * f[i] + gh * Fn[i];
+      wjm2[i] = y[i];
+      y[i] = wj;
     }
     ajm1 = 1.0 - bj * Tj;
     bjm2 = bjm1;
@@ -263,19 +286,19 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L,
     Dm2 = Dm1; Dm1 = Dj;
     Em2 = Em1; Em1 = Ej;
   }
-  copy(y, wjm1);
 }
 
-// Nonlinear power method (Appendix): v holds the eigenvector estimate between
-// calls; Fv is scratch.  Returns 1.2 sigma and the iteration count.
+// Nonlinear power method (Appendix).  The eigenvector estimate v lives in the
+// lane's LDS column (v[i * kLdsStride]) between calls and in registers during
+// one.  Returns 1.2 sigma and the iteration count.
 template <class Prob>
-RKMI_HD double spec_rad(const typename Prob::Lane& L,
-                                           const typename Prob::Params& prm,
-                                           const double (&y)[Prob::N], const double (&F)[Prob::N],
-                                           double hmax, int itmax, double (&v)[Prob::N],
-                                           int& iters) {
+RKMI_HD double spec_rad(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                        const double (&y)[Prob::N], const double (&F)[Prob::N], double hmax,
+                        int itmax, double* vslot, int& iters) {
   constexpr int N = Prob::N;
-  double Fv[N];
+  double v[N], Fv[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = vslot[i * kLdsStride];
   const double sq = sqrt(kUround);
   const double small = 1.0 / hmax;
   double ynrm = 0.0, vnrm = 0.0;
@@ -333,6 +356,8 @@ RKMI_HD double spec_rad(const typename Prob::Lane& L,
         if (i == ind) v[i] = y[i] - (v[i] - y[i]);
     }
   }
+#pragma unroll
+  for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = v[i];
   return 1.2 * sigma;
 }
 
@@ -348,153 +373,309 @@ RKMI_HD int rkc_stage_count(double& h, double sigma, int mmax) {
   return m;
 }
 
-// Per-lane RKC integration of one system from t0 to t1 (in place on y).
+// Integration state of one system under RKC (the paper's work array: previous
+// error and step, current step, spectral radius; the eigenvector is in LDS).
+template <int N>
+struct RkcState {
+  double yn[N], Fn[N];
+  double t, h, h_prev, err_prev, sigma;
+  double cbrt_err_prev;      // err_prev^(1/3), formed when err_prev was accepted
+  int64_t nstep, attempts;
+  int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
+  bool first, have_prev;
+};
+
+// Restart state (Sec. 3): F_n = f(t0, y0), v = F_n, no step-size memory.
 template <class Prob>
-__host__ __device__ int32_t rkc_integrate(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                                 const Ctl& c, double (&y)[Prob::N], int32_t (&st)[kNStats]) {
+RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                       const Ctl& c, RkcState<Prob::N>& S, double* vslot) {
   constexpr int N = Prob::N;
-  double yn[N], Fn[N], F1[N], v[N];
-  double t = c.t0;
-  const double hmax = c.hmax, hmin = c.hmin_rkc;
-  int32_t status = kSysOk;
-  int64_t attempts = 0;
-  int32_t n_acc = 0, n_rej = 0, n_rhs = 0, n_sr = 0, n_pow = 0, max_m = 0;
-  copy(yn, y);
-  if (t < c.t1) {
-    Prob::rhs(L, prm, yn, Fn);
-    ++n_rhs;
+  S.t = c.t0;
+  S.status = kSysOk;
+  S.attempts = 0;
+  S.n_acc = S.n_rej = S.n_rhs = S.n_sr = S.n_pow = S.max_m = 0;
+  if (S.t < c.t1) {
+    Prob::rhs(L, prm, S.yn, S.Fn);
+    ++S.n_rhs;
   } else {
 #pragma unroll
-    for (int i = 0; i < N; ++i) Fn[i] = 0.0;
+    for (int i = 0; i < N; ++i) S.Fn[i] = 0.0;
   }
-  copy(v, Fn);
-  double h = 0.0, h_prev = 0.0, err_prev = 0.0, sigma = 0.0;
-  int64_t nstep = 0;
-  bool first = true, have_prev = false;
-  while (t < c.t1) {
-    if (attempts >= c.max_steps) {
-      status = kSysMaxSteps;
-      break;
-    }
-    if (1.1 * h >= fabs(c.t1 - t)) h = fabs(c.t1 - t);
-    if (nstep % c.sr_period == 0) {
-      int it;
-      sigma = spec_rad<Prob>(L, prm, yn, Fn, hmax, c.sr_itmax, v, it);
-      ++n_sr;
-      n_pow += it;
-      n_rhs += it;
-    }
-    if (first) {
-      // initial step from a trial Euler step of size min(hMax, 1/sigma)
-      h = hmax;
-      if (sigma * h > 1.0) h = 1.0 / sigma;
-      h = fmax(h, hmin);
 #pragma unroll
-      for (int i = 0; i < N; ++i) y[i] = yn[i] + h * Fn[i];
-      Prob::rhs(L, prm, y, F1);
-      ++n_rhs;
-      double e = 0.0;
+  for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = S.Fn[i];
+  S.h = S.h_prev = S.err_prev = S.sigma = S.cbrt_err_prev = 0.0;
+  S.nstep = 0;
+  S.first = true;
+  S.have_prev = false;
+}
+
+// One attempted step of the RKC driver (Sec. 3.2); returns true while the
+// system still has to step (t < t1 and no failure).
+template <class Prob>
+RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                         const Ctl& c, RkcState<Prob::N>& S, double* vslot) {
+  constexpr int N = Prob::N;
+  const double hmax = c.hmax, hmin = c.hmin_rkc;
+  if (S.attempts >= c.max_steps) {
+    S.status = kSysMaxSteps;
+    return false;
+  }
+  if (1.1 * S.h >= fabs(c.t1 - S.t)) S.h = fabs(c.t1 - S.t);
+  if (S.nstep % c.sr_period == 0) {
+    int it;
+    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, vslot, it);
+    ++S.n_sr;
+    S.n_pow += it;
+    S.n_rhs += it;
+  }
+  double y[N], F1[N];
+  if (S.first) {
+    // initial step from a trial Euler step of size min(hMax, 1/sigma)
+    double h = hmax;
+    if (S.sigma * h > 1.0) h = 1.0 / S.sigma;
+    h = fmax(h, hmin);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const double est = (F1[i] - Fn[i]) / (c.atol + c.rtol * fabs(yn[i]));
-        e += est * est;
-      }
-      const double err0 = h * sqrt(e / (double)N);
-      if (kP1 * h < hmax * sqrt(err0))
-        h = fmax(kP1 * h / sqrt(err0), hmin);
-      else
-        h = hmax;
-      first = false;
-    }
-    const int m = rkc_stage_count(h, sigma, c.mmax);
-    max_m = max(max_m, m);
-    rkc_step<Prob>(L, prm, yn, Fn, h, m, y);
+    for (int i = 0; i < N; ++i) y[i] = S.yn[i] + h * S.Fn[i];
     Prob::rhs(L, prm, y, F1);
-    n_rhs += m;
-    ++attempts;
+    ++S.n_rhs;
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      double est = 0.8 * (yn[i] - y[i]) + 0.4 * h * (Fn[i] + F1[i]);
-      est = est / (c.atol + c.rtol * fmax(fabs(y[i]), fabs(yn[i])));
+      const double est = (F1[i] - S.Fn[i]) / (c.atol + c.rtol * fabs(S.yn[i]));
       e += est * est;
     }
-    const double err = sqrt(e / (double)N);
-    if (err > 1.0 || !crm::is_finite(err)) {
-      ++n_rej;
-      h = crm::is_finite(err) ? 0.8 * h / crm::cr_pow(err, 1.0 / 3.0) : kP1 * h;
-      int it;
-      sigma = spec_rad<Prob>(L, prm, yn, Fn, hmax, c.sr_itmax, v, it);
-      ++n_sr;
-      n_pow += it;
-      n_rhs += it;
-      if (!(h >= hmin)) {
-        status = kSysHmin;
-        break;
-      }
+    const double err0 = h * sqrt(e / (double)N);
+    if (kP1 * h < hmax * sqrt(err0))
+      h = fmax(kP1 * h / sqrt(err0), hmin);
+    else
+      h = hmax;
+    S.h = h;
+    S.first = false;
+  }
+  const int m = rkc_stage_count(S.h, S.sigma, c.mmax);
+  S.max_m = max(S.max_m, m);
+  rkc_step<Prob>(L, prm, S.yn, S.Fn, S.h, m, y);
+  Prob::rhs(L, prm, y, F1);
+  S.n_rhs += m;
+  ++S.attempts;
+  double e = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double est = 0.8 * (S.yn[i] - y[i]) + 0.4 * S.h * (S.Fn[i] + F1[i]);
+    est = est / (c.atol + c.rtol * fmax(fabs(y[i]), fabs(S.yn[i])));
+    e += est * est;
+  }
+  const double err = sqrt(e / (double)N);
+  if (err > 1.0 || !crm::is_finite(err)) {
+    ++S.n_rej;
+    S.h = crm::is_finite(err) ? 0.8 * S.h / crm::cr_pow(err, 1.0 / 3.0) : kP1 * S.h;
+    int it;
+    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, vslot, it);
+    ++S.n_sr;
+    S.n_pow += it;
+    S.n_rhs += it;
+    if (!(S.h >= hmin)) {
+      S.status = kSysHmin;
+      return false;
+    }
+  } else {
+    S.t += S.h;
+    ++S.nstep;
+    ++S.n_acc;
+    // err^(1/3) and err^(2/3) share one logarithm; err^(1/3) is kept for the
+    // next accepted step, where it is err_prev^(1/3)
+    const crm::dd lerr = crm::log_of_nonneg(err);
+    const double cbrt_err = crm::pow_from_log_nonneg(err, lerr, 1.0 / 3.0);
+    double fac = 10.0;
+    if (!S.have_prev) {
+      if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
     } else {
-      t += h;
-      ++nstep;
-      ++n_acc;
-      double fac = 10.0;
-      if (!have_prev) {
-        const double t2 = crm::cr_pow(err, 1.0 / 3.0);
-        if (0.8 < fac * t2) fac = 0.8 / t2;
-      } else {
-        const double t1 = 0.8 * h * crm::cr_pow(err_prev, 1.0 / 3.0);
-        const double t2 = h_prev * crm::cr_pow(err, 2.0 / 3.0);
-        if (t1 < fac * t2) fac = t1 / t2;
-      }
-      err_prev = err;
-      h_prev = h;
-      have_prev = true;
-      copy(yn, y);
-      copy(Fn, F1);
-      h = h * fmax(kP1, fac);
-      h = fmax(hmin, fmin(hmax, h));
-      if (!all_finite(yn)) {
-        status = kSysNonFinite;
-        break;
-      }
+      const double t1 = 0.8 * S.h * S.cbrt_err_prev;
+      const double t2 = S.h_prev * crm::pow_from_log_nonneg(err, lerr, 2.0 / 3.0);
+      if (t1 < fac * t2) fac = t1 / t2;
+    }
+    S.err_prev = err;
+    S.cbrt_err_prev = cbrt_err;
+    S.h_prev = S.h;
+    S.have_prev = true;
+    copy(S.yn, y);
+    copy(S.Fn, F1);
+    S.h = S.h * fmax(kP1, fac);
+    S.h = fmax(hmin, fmin(hmax, S.h));
+    if (!all_finite(S.yn)) {
+      S.status = kSysNonFinite;
+      return false;
     }
   }
-  copy(y, yn);
-  st[kStAccept] = n_acc;
-  st[kStReject] = n_rej;
-  st[kStRhs] = n_rhs;
-  st[kStSrCalls] = n_sr;
-  st[kStPowIters] = n_pow;
-  st[kStMaxStages] = max_m;
-  return status;
+  return S.t < c.t1;
+}
+
+template <int N>
+RKMI_HD void rkc_stats(const RkcState<N>& S, int32_t (&st)[kNStats]) {
+  st[kStAccept] = S.n_acc;
+  st[kStReject] = S.n_rej;
+  st[kStRhs] = S.n_rhs;
+  st[kStSrCalls] = S.n_sr;
+  st[kStPowIters] = S.n_pow;
+  st[kStMaxStages] = S.max_m;
+}
+
+// LDS doubles per lane a kernel needs: the problem's constants, plus the
+// power-method eigenvector under RKC.
+template <class Prob, int Method>
+constexpr int lane_lds_doubles() {
+  return Prob::kLaneDoubles + (Method == kMethodRkc ? Prob::N : 0);
+}
+
+// A lane's integration of one system, in four parts: start (load state and
+// parameters, per-system constants, restart state), attempt (one attempted
+// step; false once the system is finished), finish (store).
+template <class Prob, int Method>
+struct Driver;
+
+template <class Prob>
+struct Driver<Prob, kMethodRkck> {
+  static constexpr int N = Prob::N;
+  typename Prob::Lane L;
+  RkckState<N> S;
+  RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
+                     const double* y0, const double* g, double* slot) {
+    Prob::init(L, prm, g, i, n, slot);
+#pragma unroll
+    for (int k = 0; k < N; ++k) S.y[k] = y0[(int64_t)k * n + i];
+    rkck_begin<Prob>(S, c);
+    return S.t < c.t1;
+  }
+  RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double*) {
+    return rkck_attempt<Prob>(L, prm, c, S);
+  }
+  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.y[k];
+    int32_t st[kNStats];
+    rkck_stats(S, st);
+    if (status) status[i] = S.status;
+    if (stats)
+#pragma unroll
+      for (int r = 0; r < kNStats; ++r) stats[(int64_t)r * n + i] = st[r];
+  }
+};
+
+template <class Prob>
+struct Driver<Prob, kMethodRkc> {
+  static constexpr int N = Prob::N;
+  typename Prob::Lane L;
+  RkcState<N> S;
+  static RKMI_HD double* vslot(double* slot) { return slot + Prob::kLaneDoubles * kLdsStride; }
+  RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
+                     const double* y0, const double* g, double* slot) {
+    Prob::init(L, prm, g, i, n, slot);
+#pragma unroll
+    for (int k = 0; k < N; ++k) S.yn[k] = y0[(int64_t)k * n + i];
+    rkc_begin<Prob>(L, prm, c, S, vslot(slot));
+    return S.t < c.t1;
+  }
+  RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
+    return rkc_attempt<Prob>(L, prm, c, S, vslot(slot));
+  }
+  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.yn[k];
+    int32_t st[kNStats];
+    rkc_stats(S, st);
+    if (status) status[i] = S.status;
+    if (stats)
+#pragma unroll
+      for (int r = 0; r < kNStats; ++r) stats[(int64_t)r * n + i] = st[r];
+  }
+};
+
+// One whole integration of system i by the lane.
+template <class Prob, int Method>
+RKMI_HD void integrate_system(const typename Prob::Params& prm, int64_t n, int64_t i,
+                              const double* y0, double* y1, const double* g, const Ctl& c,
+                              int32_t* status, int32_t* stats, double* slot) {
+  Driver<Prob, Method> D;
+  if (D.start(prm, c, n, i, y0, g, slot))
+    while (D.attempt(prm, c, slot)) {
+    }
+  D.finish(n, i, y1, status, stats);
 }
 
 // =========================================================================
-// Plain kernels: one lane per system, struct-of-arrays loads and stores.
+// Kernels
 // =========================================================================
+
+// Plain kernel: one lane per system, system i = global thread index (the
+// paper's intDriver, Sec. 3).
 template <class Prob, int Method>
-__global__ __launch_bounds__(64) void plain_kernel(typename Prob::Params prm, int64_t n,
-                                                   const double* y0,  // may alias y1
-                                                   double* y1,
-                                                   const double* __restrict__ g, Ctl c,
-                                                   int32_t* __restrict__ status,
-                                                   int32_t* __restrict__ stats) {
-  constexpr int N = Prob::N;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLdsStride) void plain_kernel(typename Prob::Params prm, int64_t n,
+                                                           const double* y0,  // may alias y1
+                                                           double* y1,
+                                                           const double* __restrict__ g, Ctl c,
+                                                           int32_t* __restrict__ status,
+                                                           int32_t* __restrict__ stats) {
+  constexpr int kLds = lane_lds_doubles<Prob, Method>();
+  __shared__ double lds[(kLds > 0 ? kLds : 1) * kLdsStride];
+  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n) return;
-  typename Prob::Lane L;
-  Prob::init(L, prm, g, i, n);
-  double y[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) y[k] = y0[(int64_t)k * n + i];
-  int32_t st[kNStats];
-  int32_t s = (Method == 0) ? rkck_integrate<Prob>(L, prm, c, y, st)
-                            : rkc_integrate<Prob>(L, prm, c, y, st);
-#pragma unroll
-  for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = y[k];
-  if (status) status[i] = s;
-  if (stats) {
-#pragma unroll
-    for (int r = 0; r < kNStats; ++r) stats[(int64_t)r * n + i] = st[r];
+  integrate_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats, lds + threadIdx.x);
+}
+
+// Persistent kernel: a grid sized to the machine; finished lanes take the next
+// systems from a device-wide queue while the other lanes of their wave carry
+// on, so lanes are not left idle behind the slowest system of a fixed group.
+// A wave refills once at least c.refill of its lanes are idle (or all its
+// live lanes are): the systems started together form a cohort that runs its
+// set-up and its periodic spectral-radius estimates in step, instead of each
+// new lane running them alone.  The lanes taking work share one atomic add
+// (wave-aggregated).  The queue head is queue[0] and must be zero at launch.
+// A lane retires once the queue is exhausted; the wave exits when all its
+// lanes have retired, so every wave terminates.
+template <class Prob, int Method>
+__global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::Params prm,
+                                                                int64_t n, const double* y0,
+                                                                double* y1,
+                                                                const double* __restrict__ g,
+                                                                Ctl c, int32_t* __restrict__ status,
+                                                                int32_t* __restrict__ stats,
+                                                                unsigned long long* queue) {
+  constexpr int kLds = lane_lds_doubles<Prob, Method>();
+  __shared__ double lds[(kLds > 0 ? kLds : 1) * kLdsStride];
+  const int lane = threadIdx.x;
+  double* slot = lds + lane;
+  Driver<Prob, Method> D;
+  int64_t i = -1;
+  bool active = false, retired = false;
+  for (;;) {
+    const bool idle = !active && !retired;
+    const unsigned long long idle_mask = __ballot(idle);
+    const bool refill =
+        idle_mask && (__popcll(idle_mask) >= c.refill || !__ballot(active));
+    const bool need = refill && idle;
+    const unsigned long long need_mask = refill ? idle_mask : 0ull;
+    if (need_mask) {
+      const int leader = __ffsll((long long)need_mask) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(need_mask));
+      base = __shfl(base, leader);
+      if (need) {
+        const unsigned long long below = need_mask & ((1ull << lane) - 1ull);
+        const unsigned long long idx = base + (unsigned long long)__popcll(below);
+        if (idx < (unsigned long long)n) {
+          i = (int64_t)idx;
+          active = D.start(prm, c, n, i, y0, g, slot);
+          if (!active) D.finish(n, i, y1, status, stats);
+        } else {
+          retired = true;
+        }
+      }
+    }
+    if (!__ballot(!retired)) break;
+    if (active && !D.attempt(prm, c, slot)) {
+      D.finish(n, i, y1, status, stats);
+      active = false;
+    }
   }
 }
 

@@ -4,48 +4,75 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "rk_device.hpp"
 #include "rk_types.hpp"
 
 namespace rkmi {
 
-constexpr int kPlainBlock = 64;
+enum : int { kSchedAuto = 0, kSchedPlain = 1, kSchedPersistent = 2 };
 
-template <class Prob>
-int launch_plain(const LaunchArgs* a, void* stream) {
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t blocks = (a->n + kPlainBlock - 1) / kPlainBlock;
+// Bytes of workspace the persistent schedule needs (the queue head).
+constexpr size_t kQueueBytes = 256;
+
+// Idle lanes that make a wave of the persistent kernel take new systems.
+constexpr int kDefaultRefill = 16;
+
+template <int = 0>
+__global__ void queue_reset_kernel(unsigned long long* queue) {
+  queue[0] = 0ull;
+}
+
+template <class Prob, int Method>
+int launch_method(const LaunchArgs* a, hipStream_t s) {
+  const int64_t blocks = (a->n + kLdsStride - 1) / kLdsStride;
   if (blocks <= 0) return 0;
   if (blocks > 0x7fffffffLL) return -1;
-  const dim3 grid((unsigned)blocks), block(kPlainBlock);
   const typename Prob::Params prm = a->prm;
-  if (a->method == kMethodRkck)
-    plain_kernel<Prob, kMethodRkck><<<grid, block, 0, s>>>(prm, a->n, a->y0, a->y1, a->g, a->ctl,
-                                                           a->status, a->stats);
-  else
-    plain_kernel<Prob, kMethodRkc><<<grid, block, 0, s>>>(prm, a->n, a->y0, a->y1, a->g, a->ctl,
-                                                          a->status, a->stats);
+  const bool persistent = a->schedule != kSchedPlain && a->ws && a->ws_bytes >= kQueueBytes;
+  if (!persistent) {
+    plain_kernel<Prob, Method><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
+  // one resident wave per slot the occupancy allows on every compute unit
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Prob, Method>,
+                                                   kLdsStride, 0) != hipSuccess)
+    return -3;
+  if (per_cu < 1) per_cu = 1;
+  int64_t grid = (int64_t)cus * per_cu;
+  if (grid > blocks) grid = blocks;
+  unsigned long long* queue = static_cast<unsigned long long*>(a->ws);
+  queue_reset_kernel<><<<1, 1, 0, s>>>(queue);
+  persistent_kernel<Prob, Method><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
+      prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-// The per-system code of plain_kernel, run on the host for every system
-// (test hook: the same source compiled for the CPU).
+template <class Prob>
+int launch(const LaunchArgs* a, void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  return a->method == kMethodRkck ? launch_method<Prob, kMethodRkck>(a, s)
+                                  : launch_method<Prob, kMethodRkc>(a, s);
+}
+
+// The per-system code of the kernels, run on the host for every system (test
+// hook: the same source compiled for the CPU; each system is independent, so
+// the schedule does not change any result).
 template <class Prob>
 int host_run(const LaunchArgs* a) {
-  constexpr int N = Prob::N;
-  const typename Prob::Params prm = a->prm;
+  std::vector<double> slot((Prob::kLaneDoubles + Prob::N) * kLdsStride);
   for (int64_t i = 0; i < a->n; ++i) {
-    typename Prob::Lane L;
-    Prob::init(L, prm, a->g, i, a->n);
-    double y[N];
-    for (int k = 0; k < N; ++k) y[k] = a->y0[(int64_t)k * a->n + i];
-    int32_t st[kNStats];
-    const int32_t s = (a->method == kMethodRkck) ? rkck_integrate<Prob>(L, prm, a->ctl, y, st)
-                                                 : rkc_integrate<Prob>(L, prm, a->ctl, y, st);
-    for (int k = 0; k < N; ++k) a->y1[(int64_t)k * a->n + i] = y[k];
-    if (a->status) a->status[i] = s;
-    if (a->stats)
-      for (int r = 0; r < kNStats; ++r) a->stats[(int64_t)r * a->n + i] = st[r];
+    if (a->method == kMethodRkck)
+      integrate_system<Prob, kMethodRkck>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
+                                          a->stats, slot.data());
+    else
+      integrate_system<Prob, kMethodRkc>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
+                                         a->stats, slot.data());
   }
   return 0;
 }

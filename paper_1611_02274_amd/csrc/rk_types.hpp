@@ -20,7 +20,7 @@ struct Ctl {
   int mmax;           // RKC stage cap round(sqrt(rtol / (10 UROUND))), >= 2
   int sr_period;      // spectral radius every sr_period accepted steps (25)
   int sr_itmax;       // power-method iterations (50)
-  int pad;
+  int refill;         // persistent schedule: idle lanes that trigger a refill (1..64)
 };
 
 // Arguments of one integration launch (device pointers, launch-uniform controls).

@@ -6,12 +6,13 @@ namespace rkmi {
 
 struct VdpProblem {
   static constexpr int N = 2;
+  static constexpr int kLaneDoubles = 0;
   using Params = const double*;
   struct Lane {
     double mu;
   };
-  RKMI_HD static void init(Lane& L, const Params&, const double* __restrict__ g,
-                                              int64_t i, int64_t) {
+  RKMI_HD static void init(Lane& L, const Params&, const double* __restrict__ g, int64_t i,
+                           int64_t, double*) {
     L.mu = g[i];
   }
   RKMI_HD static void rhs(const Lane& L, const Params&, const double (&y)[2],
@@ -24,7 +25,7 @@ struct VdpProblem {
 }  // namespace rkmi
 
 extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s) {
-  return rkmi::launch_plain<rkmi::VdpProblem>(a, s);
+  return rkmi::launch<rkmi::VdpProblem>(a, s);
 }
 
 extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a) {

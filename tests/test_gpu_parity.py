@@ -196,3 +196,28 @@ def test_device_math_equals_host_and_oracle(rk, orc):
         m = 20000
         r = np.array([ref[fn](v) if fn < 2 else orc.cr_pow(v, w) for v, w in zip(x[:m], y[:m])])
         assert np.array_equal(dev[:m], r)
+
+
+@pytest.mark.parametrize("problem,method,n,t1,T_range", [
+    ("net13", "rkc", 5000, 1e-6, (1000.0, 2500.0)),
+    ("net9", "rkc", 3000, 1e-6, (800.0, 3000.0)),
+    ("net13", "rkck", 800, 2e-8, (1000.0, 2500.0)),
+    ("vdp", "rkck", 3000, 10.0, None),
+])
+def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
+    """The plain and the persistent (queue-refilled) schedules give identical
+    bits, and both equal the oracle."""
+    import torch
+    say(f"case schedules {problem} {method} n={n}")
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, 21)
+        prob, pb, atol = rk.Problem.vdp(), orc.vdp(), 1e-10
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, 21, T_range)
+        prob, pb, atol = rk.Problem.network(net), orc.network(net), 1e-12
+    res = [_gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, atol, schedule=s) for s in (1, 2)]
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+    yo, so, sto = _orc(orc, method, pb, y0, g, 0.0, t1, 1e-8, atol)
+    compare(*res[1], yo, so, sto, atol, f"persistent {method}/{problem}")
