@@ -120,10 +120,13 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
     /* Species equations of Sec. 4.2 at constant T: dY_k/dt = W_k omega_k / rho,
      * omega_k = sum_j nu_kj q_j, C_k = rho Y_k / W_k.  Convention for this
      * synthetic network: reversible reactions, q_j = k_f prod_R C - k_r prod_P C,
-     * a one-species side multiplied by the total concentration [M]. */
+     * a one-species side multiplied by the total concentration [M].  Both
+     * conversions are evaluated left to right as written, (rho Y_k) / W_k and
+     * (W_k omega_k) / rho, each division by a constant of the system being a
+     * multiplication by its reciprocal. */
     double C[ORC_MAXN], omega[ORC_MAXN];
     double M = 0.0;
-    for (int k = 0; k < N; ++k) C[k] = (S->rho * S->invW[k]) * y[k];
+    for (int k = 0; k < N; ++k) C[k] = (S->rho * y[k]) * S->invW[k];
     for (int k = 0; k < N; ++k) M += C[k];
     for (int k = 0; k < N; ++k) omega[k] = 0.0;
     for (int j = 0; j < pb->n_rx; ++j) {
@@ -137,7 +140,7 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
       omega[p0] += q;
       if (p1 >= 0) omega[p1] += q;
     }
-    for (int k = 0; k < N; ++k) f[k] = (pb->W[k] * S->irho) * omega[k];
+    for (int k = 0; k < N; ++k) f[k] = (pb->W[k] * omega[k]) * S->irho;
   }
 }
 
@@ -168,7 +171,7 @@ static void rhs_vjp(const orc_sys *S, const double *y, const double *u, double *
   } else {
     double C[ORC_MAXN], uw[ORC_MAXN], Cbar[ORC_MAXN];
     double M = 0.0, Mbar = 0.0;
-    for (int k = 0; k < N; ++k) C[k] = (S->rho * S->invW[k]) * y[k];
+    for (int k = 0; k < N; ++k) C[k] = (S->rho * y[k]) * S->invW[k];
     for (int k = 0; k < N; ++k) M += C[k];
     /* u^T f = sum_k (W_k/rho) u_k omega_k */
     for (int k = 0; k < N; ++k) uw[k] = (pb->W[k] * S->irho) * u[k];

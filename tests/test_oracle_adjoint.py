@@ -68,7 +68,10 @@ def test_vdp_adjoint_vs_fd(orc):
 
 def test_network_adjoint_vs_fd(orc):
     """13-species network, loss w . y(t1): dL/dY0 and dL/dlnA against central
-    differences (absolute step 1e-6) of the replayed step sequence."""
+    differences (absolute step 1e-6) of the replayed step sequence, as a
+    relative error of each gradient vector (max norm): a central difference
+    carries a rounding error of order eps |L| / h in every component, which
+    small components cannot resolve one by one."""
     net = I.standard_network(13)
     pb = orc.network(net)
     y0, g = I.kinetics_inputs(net, 2, 5005)
@@ -79,19 +82,25 @@ def test_network_adjoint_vs_fd(orc):
         assert st == orc.OK
         dy0, dlnA = orc.rkc_replay_adjoint(pb, gi, yi, 0.0, hs, ss, wi)
         e = 1e-6
+        fd_y = np.empty(13)
         for m in range(13):
             d = np.zeros(13)
             d[m] = e
-            fd = (_loss(orc, pb, gi, yi + d, hs, ss, wi) -
-                  _loss(orc, pb, gi, yi - d, hs, ss, wi)) / (2 * e)
-            assert dy0[m] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(dy0).max())
-        for j in range(0, net.n_rx, 3):
+            fd_y[m] = (_loss(orc, pb, gi, yi + d, hs, ss, wi) -
+                       _loss(orc, pb, gi, yi - d, hs, ss, wi)) / (2 * e)
+        assert np.abs(dy0 - fd_y).max() <= 1e-6 * np.abs(fd_y).max()
+        cols = np.arange(0, net.n_rx, 3)
+        fd_a = np.empty(len(cols))
+        for c, j in enumerate(cols):
             d = np.zeros(net.n_rx)
             d[j] = e
             fp = _loss(orc, pb.with_lnA(net.lnA + d), gi, yi, hs, ss, wi)
             fm = _loss(orc, pb.with_lnA(net.lnA - d), gi, yi, hs, ss, wi)
-            fd = (fp - fm) / (2 * e)
-            assert dlnA[j] == pytest.approx(fd, rel=1e-6, abs=1e-7 * np.abs(dlnA).max())
+            fd_a[c] = (fp - fm) / (2 * e)
+        assert np.abs(dlnA[cols] - fd_a).max() <= 1e-6 * np.abs(fd_a).max()
+        # the components that carry the gradient agree one by one as well
+        big = np.abs(fd_a) > 1e-2 * np.abs(fd_a).max()
+        np.testing.assert_allclose(dlnA[cols][big], fd_a[big], rtol=1e-5)
 
 
 def test_adjoint_batch_matches_single(orc):
