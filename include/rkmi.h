@@ -130,13 +130,21 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
 #define RK_SCHED_PLAIN 1
 #define RK_SCHED_PERSISTENT 2
 
-/* Device workspace (bytes) the integrators use for n_sys systems under *opt
- * (NULL = defaults): 0 for the plain schedule, a small queue block for the
- * persistent one.  The caller allocates it; it must not be shared by calls
- * that may run concurrently. */
-size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options *opt);
 #define RK_METHOD_RKCK 0
 #define RK_METHOD_RKC 1
+
+/* Device workspace (bytes) an integration of n_sys systems by `method` needs
+ * under *opt (NULL = defaults) on the current device.  Layout: a 256-byte
+ * queue head, then per-workgroup blocks of per-lane columns.  Systems of up to
+ * 16 unknowns keep their vectors in registers: 0 bytes for the plain schedule,
+ * the queue head for the persistent one.  Larger systems keep every vector and
+ * their rate constants in the workspace: one block per 64 systems for the
+ * plain schedule, one per resident workgroup for the persistent one (a smaller
+ * workspace, down to one block, runs a smaller persistent grid).  RK_SCHED_AUTO
+ * sizes for the persistent schedule.  Returns 0 on a NULL handle or bad
+ * method.  The caller allocates it; it must not be shared by calls that may
+ * run concurrently. */
+size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options *opt);
 
 /* RKCK integration of n_sys systems from t0 to t1 (Sec. 2.1, Sec. 3.1):
  *   y0     [N][n_sys]  initial states

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # Networks compiled into the library (species counts of the standard networks).
-COMPILED_NETWORKS = (9, 13)
+COMPILED_NETWORKS = (9, 13, 32, 53)
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -16,6 +16,7 @@
 
 extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s);
 extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a);
+extern "C" int64_t rkmi_vdp_workspace(int method, int schedule, int64_t n);
 
 namespace rkmi {
 extern const GenEntry kGenRegistry[];
@@ -48,6 +49,7 @@ struct rk_problem_s {
   int n_eq = 0, n_param = 0, n_theta = 0, n_rx = 0;
   rkmi::launch_fn launch = nullptr;
   rkmi::host_fn host = nullptr;
+  rkmi::workspace_fn workspace = nullptr;
   std::vector<double> host_prm;        // uniform problem data, device layout
   double* dev_prm[kMaxDevices] = {};   // per-device copies, made on first use
   std::mutex mu;
@@ -156,9 +158,6 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedPersistent)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
-    if (opt->schedule == rkmi::kSchedPersistent && (!ws || ws_bytes < rkmi::kQueueBytes))
-      return fail(RK_EWORKSPACE, "the persistent schedule needs %zu bytes of workspace",
-                  (size_t)rkmi::kQueueBytes);
   }
   if (n == 0) return RK_OK;
   int rc;
@@ -182,6 +181,10 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
   if ((rc = problem_device_data(p, &a.prm))) return rc;
   rc = p->launch(&a, stream);
+  if (rc == rkmi::kLaunchWorkspace)
+    return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (rk_workspace_bytes gives "
+                "the size this call needs)", ws ? ws_bytes : (size_t)0);
+  if (rc == rkmi::kLaunchInvalid) return fail(RK_EINVAL, "too many systems for one launch");
   if (rc) return fail(RK_EHIP, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   return RK_OK;
 }
@@ -206,6 +209,7 @@ int rk_problem_create_vdp(rk_problem* out) {
   p->n_theta = 1;
   p->launch = rkmi_vdp_launch;
   p->host = rkmi_vdp_host;
+  p->workspace = rkmi_vdp_workspace;
   *out = p;
   return RK_OK;
 }
@@ -257,6 +261,7 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
   p->n_rx = d->n_rx;
   p->launch = hit->launch;
   p->host = hit->host;
+  p->workspace = hit->workspace;
   const int nr = d->n_rx, ns = d->n_sp;
   p->host_prm.resize(4 * nr + 2 * ns);
   for (int j = 0; j < nr; ++j) {
@@ -297,10 +302,17 @@ int rk_problem_dims(rk_problem p, int32_t* n_eq, int32_t* n_param, int32_t* n_th
 }
 
 size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options* opt) {
-  (void)p;
-  (void)method;
-  if (n_sys <= 0 || (opt && opt->schedule == rkmi::kSchedPlain)) return 0;
-  return rkmi::kQueueBytes;
+  g_err.clear();
+  if (!p || n_sys <= 0 || (method != RK_METHOD_RKCK && method != RK_METHOD_RKC)) return 0;
+  const int schedule = opt ? opt->schedule : rkmi::kSchedAuto;
+  if (schedule < rkmi::kSchedAuto || schedule > rkmi::kSchedPersistent) return 0;
+  const int64_t b = p->workspace(method == RK_METHOD_RKCK ? rkmi::kMethodRkck : rkmi::kMethodRkc,
+                                 schedule, n_sys);
+  if (b < 0) {
+    fail(RK_EHIP, "could not query the current device");
+    return 0;
+  }
+  return (size_t)b;
 }
 
 int rk_integrate_rkck(rk_problem p, int64_t n_sys, const double* y0, double* y1, const double* g,

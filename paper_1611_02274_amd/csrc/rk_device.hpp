@@ -20,17 +20,28 @@
 //
 // A problem type Prob supplies
 //   static constexpr int N;             unknowns
-//   static constexpr int kLaneDoubles;  per-system constants kept in LDS
+//   static constexpr bool kColumns;     vectors in slot columns (else registers)
+//   static constexpr int kLaneDoubles;  per-system constants kept in the slot
 //   using Params;                       uniform data passed by value
 //   struct Lane;                        per-system constants kept in registers
 //   static void init(Lane&, const Params&, const double* g, int64_t i, int64_t n,
 //                    double* slot);     slot[j * kLdsStride], j < kLaneDoubles
-//   static void rhs(const Lane&, const Params&, const double (&y)[N], double (&f)[N]);
+//   template <class VI, class VO>
+//   static void rhs(const Lane&, const Params&, const VI& y, VO& f);
 // Every right-hand side here is autonomous, so stage times are not formed.
+//
+// The slot of a lane is a set of columns with stride kLdsStride (the lanes of
+// a wave interleaved, so a wave's access to one element is one contiguous
+// 512-byte row): first the problem's kLaneDoubles constants, then vectors of
+// N doubles.  Small systems keep their vectors in registers and their slot in
+// LDS; large ones (kColumns) keep every vector in slot columns in a device
+// workspace, with the right-hand side outlined as one function.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "crmath.hpp"
 #include "rk_types.hpp"
@@ -52,17 +63,94 @@ constexpr int kLdsStride = 64;
 enum : int32_t { kSysOk = 0, kSysNonFinite = 1, kSysHmin = 2, kSysMaxSteps = 3 };
 enum : int { kStAccept = 0, kStReject, kStRhs, kStSrCalls, kStPowIters, kStMaxStages, kNStats };
 
+// A vector of N unknowns held in registers.
 template <int N>
-RKMI_HD bool all_finite(const double (&y)[N]) {
+struct RegVec {
+  double a[N];
+  RKMI_HD double& operator[](int k) { return a[k]; }
+  RKMI_HD const double& operator[](int k) const { return a[k]; }
+};
+
+// A vector of N unknowns held in a slot column: element k at p[k * kLdsStride].
+template <int N>
+struct ColVec {
+  double* p;
+  RKMI_HD double& operator[](int k) const { return p[k * kLdsStride]; }
+};
+
+template <class Prob>
+using Vec = typename std::conditional<Prob::kColumns, ColVec<Prob::N>, RegVec<Prob::N>>::type;
+
+// Start of vector column `col` in a lane's slot.
+template <class Prob>
+RKMI_HD double* col_ptr(double* slot, int col) {
+  return slot + (Prob::kLaneDoubles + col * Prob::N) * kLdsStride;
+}
+
+// A work vector: column `col` of the slot, or fresh registers.
+template <class Prob>
+RKMI_HD Vec<Prob> work_vec(double* slot, int col) {
+  if constexpr (Prob::kColumns) {
+    return ColVec<Prob::N>{col_ptr<Prob>(slot, col)};
+  } else {
+    (void)slot;
+    (void)col;
+    Vec<Prob> v;
+    return v;
+  }
+}
+
+// Column layouts of the two drivers (RKC's column 0, the power-method
+// eigenvector, is also used by register-held systems).
+enum : int { kCkY = 0, kCkF, kCkYt, kCkYe, kCkK1, kCkK2, kCkK3, kCkK4, kCkK5, kCkZ, kCkFs, kCkCols };
+enum : int { kCV = 0, kCYn, kCFn, kCY, kCF1, kCWm2, kCFs, kCFv, kCCols };
+
+// Doubles per lane of the slot a kernel needs.
+template <class Prob, int Method>
+constexpr int slot_doubles() {
+  return Prob::kColumns ? Prob::kLaneDoubles + Prob::N * (Method == kMethodRkck ? kCkCols : kCCols)
+                        : Prob::kLaneDoubles + (Method == kMethodRkc ? Prob::N : 0);
+}
+
+// The right-hand side over slot columns as one outlined function, so its code
+// is not repeated at every call site.
+template <class Prob>
+__attribute__((noinline)) RKMI_HD void rhs_outlined(typename Prob::Lane L,
+                                                    typename Prob::Params prm, double* y,
+                                                    double* f) {
+  const ColVec<Prob::N> yv{y};
+  ColVec<Prob::N> fv{f};
+  Prob::rhs(L, prm, yv, fv);
+}
+
+template <class Prob, class VI, class VO>
+RKMI_HD void eval_rhs(const typename Prob::Lane& L, const typename Prob::Params& prm, const VI& y,
+                      VO& f) {
+  if constexpr (Prob::kColumns)
+    rhs_outlined<Prob>(L, prm, y.p, f.p);
+  else
+    Prob::rhs(L, prm, y, f);
+}
+
+// Loops over the unknowns are unrolled for register-held vectors (constant
+// register indices); over slot columns they are unrolled by 8, so a lane has
+// eight independent loads in flight without keeping whole vectors live.
+template <class Prob>
+constexpr int kUnroll = Prob::kColumns ? 8 : Prob::N;
+
+template <class Prob, class V>
+RKMI_HD bool all_finite(const V& y) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
   bool ok = true;
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) ok = ok && crm::is_finite(y[i]);
   return ok;
 }
 
-template <int N>
-RKMI_HD void copy(double (&d)[N], const double (&s)[N]) {
-#pragma unroll
+template <class Prob, class VD, class VS>
+RKMI_HD void copy(VD& d, const VS& s) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
+#pragma unroll U
   for (int i = 0; i < N; ++i) d[i] = s[i];
 }
 
@@ -86,42 +174,45 @@ constexpr double e1 = -277.0 / 64512.0, e3 = 6925.0 / 370944.0, e4 = -6925.0 / 2
 // fifth-order solution and the error estimate sum_i (c_i - c*_i) k_i.
 template <class Prob>
 RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                        const double (&y)[Prob::N], const double (&F)[Prob::N], double h,
-                        double (&yt)[Prob::N], double (&ye)[Prob::N]) {
-  constexpr int N = Prob::N;
-  double k1[N], k2[N], k3[N], k4[N], k5[N], z[N], f[N];
-#pragma unroll
+                        const Vec<Prob>& y, const Vec<Prob>& F, double h, Vec<Prob>& yt,
+                        Vec<Prob>& ye, double* slot) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
+  Vec<Prob> k1 = work_vec<Prob>(slot, kCkK1), k2 = work_vec<Prob>(slot, kCkK2),
+            k3 = work_vec<Prob>(slot, kCkK3), k4 = work_vec<Prob>(slot, kCkK4),
+            k5 = work_vec<Prob>(slot, kCkK5), z = work_vec<Prob>(slot, kCkZ),
+            f = work_vec<Prob>(slot, kCkFs);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     k1[i] = h * F[i];
     z[i] = y[i] + ck::b21 * k1[i];
   }
-  Prob::rhs(L, prm, z, f);
-#pragma unroll
+  eval_rhs<Prob>(L, prm, z, f);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     k2[i] = h * f[i];
     z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
   }
-  Prob::rhs(L, prm, z, f);
-#pragma unroll
+  eval_rhs<Prob>(L, prm, z, f);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     k3[i] = h * f[i];
     z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
   }
-  Prob::rhs(L, prm, z, f);
-#pragma unroll
+  eval_rhs<Prob>(L, prm, z, f);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     k4[i] = h * f[i];
     z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
   }
-  Prob::rhs(L, prm, z, f);
-#pragma unroll
+  eval_rhs<Prob>(L, prm, z, f);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     k5[i] = h * f[i];
     z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
            ck::b65 * k5[i];
   }
-  Prob::rhs(L, prm, z, f);
-#pragma unroll
+  eval_rhs<Prob>(L, prm, z, f);
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     const double k6 = h * f[i];
     yt[i] = y[i] + ck::c1 * k1[i] + ck::c3 * k3[i] + ck::c4 * k4[i] + ck::c6 * k6;
@@ -130,17 +221,29 @@ RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Param
 }
 
 // Integration state of one system under RKCK.
-template <int N>
+template <class Prob>
 struct RkckState {
-  double y[N], F[N];
+  Vec<Prob> y, F;
   double t, h;
   int64_t attempts;
   int32_t n_acc, n_rej, n_rhs, status;
   bool fvalid;
 };
 
+// Points the state's vectors at their slot columns (column storage only).
 template <class Prob>
-RKMI_HD void rkck_begin(RkckState<Prob::N>& S, const Ctl& c) {
+RKMI_HD void rkck_bind(RkckState<Prob>& S, double* slot) {
+  if constexpr (Prob::kColumns) {
+    S.y.p = col_ptr<Prob>(slot, kCkY);
+    S.F.p = col_ptr<Prob>(slot, kCkF);
+  } else {
+    (void)S;
+    (void)slot;
+  }
+}
+
+template <class Prob>
+RKMI_HD void rkck_begin(RkckState<Prob>& S, const Ctl& c) {
   S.t = c.t0;
   S.h = 0.5 * c.hmax;
   S.fvalid = false;
@@ -149,32 +252,30 @@ RKMI_HD void rkck_begin(RkckState<Prob::N>& S, const Ctl& c) {
   S.n_acc = S.n_rej = S.n_rhs = 0;
 }
 
-RKMI_HD bool rkck_running(const RkckState<1>&, const Ctl&) { return true; }
-
 // One attempted step of the RKCK driver (Sec. 3.1); returns true while the
 // system still has to step (t < t1 and no failure).
 template <class Prob>
 RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                          const Ctl& c, RkckState<Prob::N>& S) {
-  constexpr int N = Prob::N;
+                          const Ctl& c, RkckState<Prob>& S, double* slot) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
   if (S.attempts >= c.max_steps) {
     S.status = kSysMaxSteps;
     return false;
   }
   S.h = fmin(c.t1 - S.t, S.h);
   if (!S.fvalid) {
-    Prob::rhs(L, prm, S.y, S.F);
+    eval_rhs<Prob>(L, prm, S.y, S.F);
     ++S.n_rhs;
     S.fvalid = true;
   }
-  double yt[N], ye[N];
-  rkck_trial<Prob>(L, prm, S.y, S.F, S.h, yt, ye);
+  Vec<Prob> yt = work_vec<Prob>(slot, kCkYt), ye = work_vec<Prob>(slot, kCkYe);
+  rkck_trial<Prob>(L, prm, S.y, S.F, S.h, yt, ye, slot);
   S.n_rhs += 5;
   ++S.attempts;
   // scaled error max_i |yerr_i / (|y_i| + |h F_i| + delta)| / rtol
   double err = 0.0;
   bool nan_flag = false;
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     nan_flag = nan_flag || crm::is_nan(ye[i]);
     err = fmax(err, fabs(ye[i] / (fabs(S.y[i]) + fabs(S.h * S.F[i]) + c.delta)));
@@ -194,10 +295,10 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
     S.t += S.h;
     const double hn = (err > kErrCon) ? kSafety * S.h * crm::cr_pow(err, kPGrow) : S.h * 5.0;
     S.h = fmax(kRkckHmin, fmin(c.hmax, hn));
-    copy(S.y, yt);
+    copy<Prob>(S.y, yt);
     ++S.n_acc;
     S.fvalid = false;
-    if (!all_finite(S.y)) {
+    if (!all_finite<Prob>(S.y)) {
       S.status = kSysNonFinite;
       return false;
     }
@@ -205,8 +306,8 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
   return S.t < c.t1;
 }
 
-template <int N>
-RKMI_HD void rkck_stats(const RkckState<N>& S, int32_t (&st)[kNStats]) {
+template <class Prob>
+RKMI_HD void rkck_stats(const RkckState<Prob>& S, int32_t (&st)[kNStats]) {
   st[kStAccept] = S.n_acc;
   st[kStReject] = S.n_rej;
   st[kStRhs] = S.n_rhs;
@@ -240,9 +341,9 @@ RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
 // the coefficients b_j, mu_j, nu_j, mut_j, gt_j are formed stage by stage.
 template <class Prob>
 RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                      const double (&yn)[Prob::N], const double (&Fn)[Prob::N], double h, int s,
-                      double (&y)[Prob::N]) {
-  constexpr int N = Prob::N;
+                      const Vec<Prob>& yn, const Vec<Prob>& Fn, double h, int s, Vec<Prob>& y,
+                      double* slot) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
   double w0, w1;
   rkc_omegas(s, w0, w1);
   double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
@@ -254,9 +355,9 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
   }
   double bjm1 = b2, bjm2 = b2;           // b_1 = b_0 = b_2
   double ajm1 = 1.0 - bjm1 * w0;         // a_1 = 1 - b_1 T_1
-  double wjm2[N], f[N];
+  Vec<Prob> wjm2 = work_vec<Prob>(slot, kCWm2), f = work_vec<Prob>(slot, kCFs);
   const double mh1 = (bjm1 * w1) * h;    // mut_1 h
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     wjm2[i] = yn[i];
     y[i] = yn[i] + mh1 * Fn[i];          // y holds w_{j-1}
@@ -272,8 +373,8 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
     const double gt = -ajm1 * mut;
     const double c0 = 1.0 - mu - nu;
     const double mh = mut * h, gh = gt * h;
-    Prob::rhs(L, prm, y, f);
-#pragma unroll
+    eval_rhs<Prob>(L, prm, y, f);
+#pragma unroll U
     for (int i = 0; i < N; ++i) {
       const double wj = c0 * yn[i] + mu * y[i] + nu * wjm2[i] + mh * f[i] + gh * Fn[i];
       wjm2[i] = y[i];
@@ -288,21 +389,24 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
   }
 }
 
-// Nonlinear power method (Appendix).  The eigenvector estimate v lives in the
-// lane's LDS column (v[i * kLdsStride]) between calls and in registers during
-// one.  Returns 1.2 sigma and the iteration count.
+// Nonlinear power method (Appendix).  The eigenvector estimate v lives in
+// slot column kCV between calls (and in registers during one when the system's
+// vectors are register-held).  Returns 1.2 sigma and the iteration count.
 template <class Prob>
 RKMI_HD double spec_rad(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                        const double (&y)[Prob::N], const double (&F)[Prob::N], double hmax,
-                        int itmax, double* vslot, int& iters) {
-  constexpr int N = Prob::N;
-  double v[N], Fv[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = vslot[i * kLdsStride];
+                        const Vec<Prob>& y, const Vec<Prob>& F, double hmax, int itmax,
+                        double* slot, int& iters) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
+  double* const vslot = col_ptr<Prob>(slot, kCV);
+  Vec<Prob> v = work_vec<Prob>(slot, kCV), Fv = work_vec<Prob>(slot, kCFv);
+  if constexpr (!Prob::kColumns) {
+#pragma unroll U
+    for (int i = 0; i < N; ++i) v[i] = vslot[i * kLdsStride];
+  }
   const double sq = sqrt(kUround);
   const double small = 1.0 / hmax;
   double ynrm = 0.0, vnrm = 0.0;
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     ynrm += y[i] * y[i];
     vnrm += v[i] * v[i];
@@ -313,51 +417,55 @@ RKMI_HD double spec_rad(const typename Prob::Lane& L, const typename Prob::Param
   if (ynrm != 0.0 && vnrm != 0.0) {
     dynrm = ynrm * sq;
     const double r = dynrm / vnrm;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) v[i] = y[i] + v[i] * r;
   } else if (ynrm != 0.0) {
     dynrm = ynrm * sq;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) v[i] = y[i] * (1.0 + sq);
   } else if (vnrm != 0.0) {
     dynrm = kUround;
     const double r = dynrm / vnrm;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) v[i] = v[i] * r;
   } else {
     dynrm = kUround;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) v[i] = kUround;
   }
   double sigma = 0.0;
   iters = itmax;
   for (int it = 1; it <= itmax; ++it) {
-    Prob::rhs(L, prm, v, Fv);
+    eval_rhs<Prob>(L, prm, v, Fv);
     double d = 0.0;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) d += (Fv[i] - F[i]) * (Fv[i] - F[i]);
     d = sqrt(d);
     const double sprev = sigma;
     sigma = d / dynrm;
     if (it >= 2 && fabs(sigma - sprev) <= fmax(sigma, small) * 0.01) {
-#pragma unroll
+#pragma unroll U
       for (int i = 0; i < N; ++i) v[i] = v[i] - y[i];
       iters = it;
       break;
     }
     if (d != 0.0) {
       const double r = dynrm / d;
-#pragma unroll
+#pragma unroll U
       for (int i = 0; i < N; ++i) v[i] = y[i] + (Fv[i] - F[i]) * r;
     } else {
       const int ind = it % N;
-#pragma unroll
+#pragma unroll U
       for (int i = 0; i < N; ++i)
         if (i == ind) v[i] = y[i] - (v[i] - y[i]);
     }
   }
-#pragma unroll
-  for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = v[i];
+  if constexpr (!Prob::kColumns) {
+#pragma unroll U
+    for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = v[i];
+  } else {
+    (void)vslot;
+  }
   return 1.2 * sigma;
 }
 
@@ -374,10 +482,10 @@ RKMI_HD int rkc_stage_count(double& h, double sigma, int mmax) {
 }
 
 // Integration state of one system under RKC (the paper's work array: previous
-// error and step, current step, spectral radius; the eigenvector is in LDS).
-template <int N>
+// error and step, current step, spectral radius; the eigenvector is in the slot).
+template <class Prob>
 struct RkcState {
-  double yn[N], Fn[N];
+  Vec<Prob> yn, Fn;
   double t, h, h_prev, err_prev, sigma;
   double cbrt_err_prev;      // err_prev^(1/3), formed when err_prev was accepted
   int64_t nstep, attempts;
@@ -385,23 +493,35 @@ struct RkcState {
   bool first, have_prev;
 };
 
+template <class Prob>
+RKMI_HD void rkc_bind(RkcState<Prob>& S, double* slot) {
+  if constexpr (Prob::kColumns) {
+    S.yn.p = col_ptr<Prob>(slot, kCYn);
+    S.Fn.p = col_ptr<Prob>(slot, kCFn);
+  } else {
+    (void)S;
+    (void)slot;
+  }
+}
+
 // Restart state (Sec. 3): F_n = f(t0, y0), v = F_n, no step-size memory.
 template <class Prob>
 RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                       const Ctl& c, RkcState<Prob::N>& S, double* vslot) {
-  constexpr int N = Prob::N;
+                       const Ctl& c, RkcState<Prob>& S, double* slot) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
+  double* const vslot = col_ptr<Prob>(slot, kCV);
   S.t = c.t0;
   S.status = kSysOk;
   S.attempts = 0;
   S.n_acc = S.n_rej = S.n_rhs = S.n_sr = S.n_pow = S.max_m = 0;
   if (S.t < c.t1) {
-    Prob::rhs(L, prm, S.yn, S.Fn);
+    eval_rhs<Prob>(L, prm, S.yn, S.Fn);
     ++S.n_rhs;
   } else {
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) S.Fn[i] = 0.0;
   }
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = S.Fn[i];
   S.h = S.h_prev = S.err_prev = S.sigma = S.cbrt_err_prev = 0.0;
   S.nstep = 0;
@@ -413,8 +533,8 @@ RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params
 // system still has to step (t < t1 and no failure).
 template <class Prob>
 RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                         const Ctl& c, RkcState<Prob::N>& S, double* vslot) {
-  constexpr int N = Prob::N;
+                         const Ctl& c, RkcState<Prob>& S, double* slot) {
+  constexpr int N = Prob::N, U = kUnroll<Prob>;
   const double hmax = c.hmax, hmin = c.hmin_rkc;
   if (S.attempts >= c.max_steps) {
     S.status = kSysMaxSteps;
@@ -423,23 +543,23 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   if (1.1 * S.h >= fabs(c.t1 - S.t)) S.h = fabs(c.t1 - S.t);
   if (S.nstep % c.sr_period == 0) {
     int it;
-    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, vslot, it);
+    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
     ++S.n_sr;
     S.n_pow += it;
     S.n_rhs += it;
   }
-  double y[N], F1[N];
+  Vec<Prob> y = work_vec<Prob>(slot, kCY), F1 = work_vec<Prob>(slot, kCF1);
   if (S.first) {
     // initial step from a trial Euler step of size min(hMax, 1/sigma)
     double h = hmax;
     if (S.sigma * h > 1.0) h = 1.0 / S.sigma;
     h = fmax(h, hmin);
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) y[i] = S.yn[i] + h * S.Fn[i];
-    Prob::rhs(L, prm, y, F1);
+    eval_rhs<Prob>(L, prm, y, F1);
     ++S.n_rhs;
     double e = 0.0;
-#pragma unroll
+#pragma unroll U
     for (int i = 0; i < N; ++i) {
       const double est = (F1[i] - S.Fn[i]) / (c.atol + c.rtol * fabs(S.yn[i]));
       e += est * est;
@@ -454,12 +574,12 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   }
   const int m = rkc_stage_count(S.h, S.sigma, c.mmax);
   S.max_m = max(S.max_m, m);
-  rkc_step<Prob>(L, prm, S.yn, S.Fn, S.h, m, y);
-  Prob::rhs(L, prm, y, F1);
+  rkc_step<Prob>(L, prm, S.yn, S.Fn, S.h, m, y, slot);
+  eval_rhs<Prob>(L, prm, y, F1);
   S.n_rhs += m;
   ++S.attempts;
   double e = 0.0;
-#pragma unroll
+#pragma unroll U
   for (int i = 0; i < N; ++i) {
     double est = 0.8 * (S.yn[i] - y[i]) + 0.4 * S.h * (S.Fn[i] + F1[i]);
     est = est / (c.atol + c.rtol * fmax(fabs(y[i]), fabs(S.yn[i])));
@@ -470,7 +590,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     ++S.n_rej;
     S.h = crm::is_finite(err) ? 0.8 * S.h / crm::cr_pow(err, 1.0 / 3.0) : kP1 * S.h;
     int it;
-    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, vslot, it);
+    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
     ++S.n_sr;
     S.n_pow += it;
     S.n_rhs += it;
@@ -498,11 +618,11 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     S.cbrt_err_prev = cbrt_err;
     S.h_prev = S.h;
     S.have_prev = true;
-    copy(S.yn, y);
-    copy(S.Fn, F1);
+    copy<Prob>(S.yn, y);
+    copy<Prob>(S.Fn, F1);
     S.h = S.h * fmax(kP1, fac);
     S.h = fmax(hmin, fmin(hmax, S.h));
-    if (!all_finite(S.yn)) {
+    if (!all_finite<Prob>(S.yn)) {
       S.status = kSysNonFinite;
       return false;
     }
@@ -510,21 +630,14 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   return S.t < c.t1;
 }
 
-template <int N>
-RKMI_HD void rkc_stats(const RkcState<N>& S, int32_t (&st)[kNStats]) {
+template <class Prob>
+RKMI_HD void rkc_stats(const RkcState<Prob>& S, int32_t (&st)[kNStats]) {
   st[kStAccept] = S.n_acc;
   st[kStReject] = S.n_rej;
   st[kStRhs] = S.n_rhs;
   st[kStSrCalls] = S.n_sr;
   st[kStPowIters] = S.n_pow;
   st[kStMaxStages] = S.max_m;
-}
-
-// LDS doubles per lane a kernel needs: the problem's constants, plus the
-// power-method eigenvector under RKC.
-template <class Prob, int Method>
-constexpr int lane_lds_doubles() {
-  return Prob::kLaneDoubles + (Method == kMethodRkc ? Prob::N : 0);
 }
 
 // A lane's integration of one system, in four parts: start (load state and
@@ -535,22 +648,23 @@ struct Driver;
 
 template <class Prob>
 struct Driver<Prob, kMethodRkck> {
-  static constexpr int N = Prob::N;
+  static constexpr int N = Prob::N, U = kUnroll<Prob>;
   typename Prob::Lane L;
-  RkckState<N> S;
+  RkckState<Prob> S;
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
                      const double* y0, const double* g, double* slot) {
     Prob::init(L, prm, g, i, n, slot);
-#pragma unroll
+    rkck_bind<Prob>(S, slot);
+#pragma unroll U
     for (int k = 0; k < N; ++k) S.y[k] = y0[(int64_t)k * n + i];
     rkck_begin<Prob>(S, c);
     return S.t < c.t1;
   }
-  RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double*) {
-    return rkck_attempt<Prob>(L, prm, c, S);
+  RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
+    return rkck_attempt<Prob>(L, prm, c, S, slot);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
-#pragma unroll
+#pragma unroll U
     for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.y[k];
     int32_t st[kNStats];
     rkck_stats(S, st);
@@ -563,23 +677,23 @@ struct Driver<Prob, kMethodRkck> {
 
 template <class Prob>
 struct Driver<Prob, kMethodRkc> {
-  static constexpr int N = Prob::N;
+  static constexpr int N = Prob::N, U = kUnroll<Prob>;
   typename Prob::Lane L;
-  RkcState<N> S;
-  static RKMI_HD double* vslot(double* slot) { return slot + Prob::kLaneDoubles * kLdsStride; }
+  RkcState<Prob> S;
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
                      const double* y0, const double* g, double* slot) {
     Prob::init(L, prm, g, i, n, slot);
-#pragma unroll
+    rkc_bind<Prob>(S, slot);
+#pragma unroll U
     for (int k = 0; k < N; ++k) S.yn[k] = y0[(int64_t)k * n + i];
-    rkc_begin<Prob>(L, prm, c, S, vslot(slot));
+    rkc_begin<Prob>(L, prm, c, S, slot);
     return S.t < c.t1;
   }
   RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
-    return rkc_attempt<Prob>(L, prm, c, S, vslot(slot));
+    return rkc_attempt<Prob>(L, prm, c, S, slot);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
-#pragma unroll
+#pragma unroll U
     for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.yn[k];
     int32_t st[kNStats];
     rkc_stats(S, st);
@@ -606,6 +720,22 @@ RKMI_HD void integrate_system(const typename Prob::Params& prm, int64_t n, int64
 // Kernels
 // =========================================================================
 
+// The slot of this lane: in LDS for register-held systems, else in the
+// workgroup's block of the column workspace (one block of slot_doubles
+// columns per workgroup).
+template <class Prob, int Method>
+__device__ double* lane_slot(double* lds, double* cols) {
+  if constexpr (Prob::kColumns)
+    return cols + (int64_t)blockIdx.x * (slot_doubles<Prob, Method>() * kLdsStride) + threadIdx.x;
+  else
+    return lds + threadIdx.x;
+}
+
+template <class Prob, int Method>
+constexpr int kernel_lds_doubles() {
+  return (Prob::kColumns || slot_doubles<Prob, Method>() == 0) ? 1 : slot_doubles<Prob, Method>();
+}
+
 // Plain kernel: one lane per system, system i = global thread index (the
 // paper's intDriver, Sec. 3).
 template <class Prob, int Method>
@@ -614,12 +744,13 @@ __global__ __launch_bounds__(kLdsStride) void plain_kernel(typename Prob::Params
                                                            double* y1,
                                                            const double* __restrict__ g, Ctl c,
                                                            int32_t* __restrict__ status,
-                                                           int32_t* __restrict__ stats) {
-  constexpr int kLds = lane_lds_doubles<Prob, Method>();
-  __shared__ double lds[(kLds > 0 ? kLds : 1) * kLdsStride];
+                                                           int32_t* __restrict__ stats,
+                                                           double* cols) {
+  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n) return;
-  integrate_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats, lds + threadIdx.x);
+  integrate_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats,
+                                 lane_slot<Prob, Method>(lds, cols));
 }
 
 // Persistent kernel: a grid sized to the machine; finished lanes take the next
@@ -639,11 +770,11 @@ __global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::P
                                                                 const double* __restrict__ g,
                                                                 Ctl c, int32_t* __restrict__ status,
                                                                 int32_t* __restrict__ stats,
-                                                                unsigned long long* queue) {
-  constexpr int kLds = lane_lds_doubles<Prob, Method>();
-  __shared__ double lds[(kLds > 0 ? kLds : 1) * kLdsStride];
+                                                                unsigned long long* queue,
+                                                                double* cols) {
+  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   const int lane = threadIdx.x;
-  double* slot = lds + lane;
+  double* slot = lane_slot<Prob, Method>(lds, cols);
   Driver<Prob, Method> D;
   int64_t i = -1;
   bool active = false, retired = false;

@@ -26,7 +26,7 @@ struct Ctl {
 // Arguments of one integration launch (device pointers, launch-uniform controls).
 struct LaunchArgs {
   int method;            // kMethodRkck | kMethodRkc
-  int schedule;          // reserved for alternative schedules
+  int schedule;          // kSchedAuto | kSchedPlain | kSchedPersistent
   int64_t n;             // systems
   const double* y0;      // [N][n]
   double* y1;            // [N][n]
@@ -46,6 +46,10 @@ typedef int (*launch_fn)(const LaunchArgs*, void* stream);
 // test hook that checks the kernels' arithmetic on the CPU); 0 on success.
 typedef int (*host_fn)(const LaunchArgs*);
 
+// Workspace bytes a launch of `method` over n systems needs under `schedule`
+// (auto counts as persistent); negative if the device cannot be queried.
+typedef int64_t (*workspace_fn)(int method, int schedule, int64_t n);
+
 // Compiled network: the topology it was generated for and its launchers.
 struct GenEntry {
   int n_sp;
@@ -54,6 +58,7 @@ struct GenEntry {
   const int32_t* prod;   // [n_rx][2]
   launch_fn launch;
   host_fn host;
+  workspace_fn workspace;
 };
 
 }  // namespace rkmi

@@ -6,6 +6,7 @@ namespace rkmi {
 
 struct VdpProblem {
   static constexpr int N = 2;
+  static constexpr bool kColumns = false;
   static constexpr int kLaneDoubles = 0;
   using Params = const double*;
   struct Lane {
@@ -15,8 +16,8 @@ struct VdpProblem {
                            int64_t, double*) {
     L.mu = g[i];
   }
-  RKMI_HD static void rhs(const Lane& L, const Params&, const double (&y)[2],
-                                             double (&f)[2]) {
+  template <class VI, class VO>
+  RKMI_HD static void rhs(const Lane& L, const Params&, const VI& y, VO& f) {
     f[0] = y[1];
     f[1] = L.mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
   }
@@ -30,4 +31,8 @@ extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s) {
 
 extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a) {
   return rkmi::host_run<rkmi::VdpProblem>(a);
+}
+
+extern "C" int64_t rkmi_vdp_workspace(int method, int schedule, int64_t n) {
+  return rkmi::workspace<rkmi::VdpProblem>(method, schedule, n);
 }

@@ -147,20 +147,22 @@ def test_argument_errors(rk):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n_sample", [512])
-def test_net13_rkc_full_size_sampled(rk, orc, n_sample):
-    """The 2^18-system 13-species RKC workload at full size, in the launch the
-    benchmark times; the oracle recomputes a spread sample of systems."""
-    w = I.WORKLOADS["net13_rkc"]
+@pytest.mark.parametrize("wname,n_sample", [("net13_rkc", 512), ("net53_rkc", 256),
+                                           ("net53_rkck", 256)])
+def test_full_size_sampled(rk, orc, wname, n_sample):
+    """The 2^18-system 13-species RKC and the 2^20-system 53-species RKC / RKCK
+    workloads at full size, in the launch the benchmark times; the oracle
+    recomputes a spread sample of systems."""
+    w = I.WORKLOADS[wname]
     say(f"case full-size {w.name} n={w.n}")
     net = I.network_of(w.problem)
     y0, g = I.workload_inputs(w)
     prob, pb = rk.Problem.network(net), orc.network(net)
-    yg, sg, stg = _gpu(rk, "rkc", prob, y0, g, w.t0, w.t1, w.rtol, w.atol)
+    yg, sg, stg = _gpu(rk, w.method, prob, y0, g, w.t0, w.t1, w.rtol, w.atol)
     idx = np.unique(np.linspace(0, w.n - 1, n_sample).astype(np.int64))
-    yo, so, sto = _orc(orc, "rkc", pb, np.ascontiguousarray(y0[:, idx]),
+    yo, so, sto = _orc(orc, w.method, pb, np.ascontiguousarray(y0[:, idx]),
                        np.ascontiguousarray(g[:, idx]), w.t0, w.t1, w.rtol, w.atol)
-    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, "full net13_rkc sample")
+    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, f"full {w.name} sample")
     # whole-batch properties: every system finished, mass fractions still sum to one
     assert np.all(sg == 0)
     assert np.abs(yg.sum(0) - 1.0).max() < 1e-11
@@ -203,6 +205,11 @@ def test_device_math_equals_host_and_oracle(rk, orc):
     ("net9", "rkc", 3000, 1e-6, (800.0, 3000.0)),
     ("net13", "rkck", 800, 2e-8, (1000.0, 2500.0)),
     ("vdp", "rkck", 3000, 10.0, None),
+    # vectors and rate constants in workspace columns
+    ("net53", "rkc", 700, 1e-6, (900.0, 2800.0)),
+    ("net53", "rkck", 700, 1e-6, (900.0, 2800.0)),
+    ("net32", "rkc", 700, 1e-6, (900.0, 2800.0)),
+    ("net32", "rkck", 300, 1e-6, (900.0, 2800.0)),
 ])
 def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
     """The plain and the persistent (queue-refilled) schedules give identical
@@ -221,3 +228,46 @@ def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
         assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
     yo, so, sto = _orc(orc, method, pb, y0, g, 0.0, t1, 1e-8, atol)
     compare(*res[1], yo, so, sto, atol, f"persistent {method}/{problem}")
+
+
+def test_column_workspace(rk, orc):
+    """Systems held in workspace columns: too small a workspace is refused with
+    RK_EWORKSPACE (plain and persistent); a workspace of one workgroup block
+    runs a one-workgroup persistent grid with the same bits as the full one."""
+    import ctypes as C
+    import torch
+    from paper_1611_02274_amd import _lib
+    say("case column workspace")
+    net = I.network_of("net53")
+    y0, g = I.kinetics_inputs(net, 200, 8, (900.0, 2800.0))
+    prob = rk.Problem.network(net)
+    L = _lib.lib()
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    ref, st_ref, stats_ref = rk.integrate_rkc(prob, yd, gd, 0.0, 1e-6, 1e-8, 1e-12)
+    opt = _lib.Options()
+    opt.schedule = 2
+    full = L.rk_workspace_bytes(prob.handle, 1, 200, C.byref(opt))
+    assert full > 256
+    opt.schedule = 1
+    plain = L.rk_workspace_bytes(prob.handle, 1, 200, C.byref(opt))
+    block = (plain - 256) // 4          # 200 systems = 4 workgroups
+    assert plain == 256 + 4 * block
+    out = torch.empty_like(yd)
+    st = torch.empty(200, dtype=torch.int32, device="cuda")
+    stats = torch.empty((6, 200), dtype=torch.int32, device="cuda")
+    ws = torch.empty(plain, dtype=torch.uint8, device="cuda")
+
+    def call(schedule, nbytes):
+        opt.schedule = schedule
+        return L.rk_integrate_rkc(prob.handle, 200, yd.data_ptr(), out.data_ptr(), gd.data_ptr(),
+                                  0.0, 1e-6, 1e-8, 1e-12, st.data_ptr(), stats.data_ptr(),
+                                  ws.data_ptr(), nbytes, C.byref(opt), None)
+
+    assert call(1, plain - 8) == _lib.RK_EWORKSPACE
+    assert call(2, 256 + block - 8) == _lib.RK_EWORKSPACE
+    assert call(2, 256 + block) == _lib.RK_OK
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(st, st_ref) and torch.equal(stats, stats_ref)
+    assert call(1, plain) == _lib.RK_OK
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(stats, stats_ref)

@@ -38,6 +38,11 @@ CASES = [
     ("rkc", "net13", 96, 2002, 0.0, 1e-6, 1e-8, 1e-12, (1000.0, 2500.0)),
     ("rkck", "net13", 32, 12, 0.0, 2e-8, 1e-8, 1e-12, (1000.0, 2500.0)),
     ("rkck", "net9", 32, 5, 0.0, 1e-8, 1e-6, 0.0, (800.0, 3000.0)),
+    # larger networks: vectors and rate constants in slot columns
+    ("rkc", "net32", 12, 3003, 0.0, 1e-6, 1e-8, 1e-12, (900.0, 2800.0)),
+    ("rkc", "net53", 12, 3003, 0.0, 1e-6, 1e-8, 1e-12, (900.0, 2800.0)),
+    ("rkck", "net32", 8, 31, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
+    ("rkck", "net53", 8, 3003, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
 ]
 
 
