@@ -69,12 +69,122 @@ def cpu_baseline(w, net, y0, g, target_s: float):
             "sample": f"{m} of {w.n} systems (evenly spaced), {dt:.1f} s on {cores} threads"}
 
 
+def adjoint_bench(args, w, net):
+    """One step = the taped RKC forward and the reverse sweep of the discrete
+    adjoint (checkpoint every 16 accepted steps) for L = sum w . y(t1): the
+    gradient of every system's loss with respect to y0 and ln A."""
+    import numpy as np
+    import torch
+
+    import paper_1611_02274_amd as rk
+    from paper_1611_02274_amd import flops as FL
+    from paper_1611_02274_amd import inputs as I
+
+    log(f"bench: adjoint workload {w.name} n={w.n}; generating inputs")
+    y0, g = I.workload_inputs(w)
+    wt = I.adjoint_weights(net.n_sp, w.n, w.seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = rk.Problem.network(net)
+    yd, gd, wd = (torch.from_numpy(a).to(dev) for a in (y0, g, wt))
+    K, cap = 16, 4096
+    y1, st, stats, tape = rk.integrate_rkc_taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol,
+                                                 max_accepted=cap, ckpt_every=K)
+    torch.cuda.synchronize()
+    if int(tape.count.min()) < 0:
+        raise RuntimeError("tape too short for this workload")
+    ms = int(stats[5].max())
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        rk.integrate_rkc_taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, max_accepted=cap,
+                               ckpt_every=K, out=y1, status=st, stats=stats)
+        if ev:
+            ev[1].record(stream)
+        out = rk.adjoint_rkc(prob, gd, tape, wd, max_stages=ms)
+        if ev:
+            ev[2].record(stream)
+        return out
+
+    for k in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {k + 1}/{args.warmup} done")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        dy0, dth, ast = step(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    rev_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s; forward {fwd_ms:.3f} ms, "
+        f"reverse {rev_ms:.3f} ms")
+    st_h = stats.cpu().numpy()
+    # accepted steps and their stage counts, from the tape
+    n, cnt = w.n, tape.count.to(torch.int64)
+    s_tab = tape.s
+    mask = torch.arange(cap, device=dev)[:, None] < cnt[None, :]
+    n_steps = float(cnt.sum())
+    stage_sum = float((s_tab.to(torch.int64) * mask).sum())
+    fwd_flops = FL.total("rkc", st_h, prob.n_eq, net)
+    rev_flops = FL.adjoint_reverse(prob.n_eq, net, n_steps, stage_sum)
+    dom_ms, dom_flops, dom = ((rev_ms, rev_flops, "adjoint_kernel") if rev_ms >= fwd_ms
+                              else (fwd_ms, fwd_flops, "taped_kernel"))
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    value = w.n * args.steps / elapsed
+    res = {
+        "metric": METRIC, "value": value, "unit": "grads/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "method": "rkc discrete adjoint", "problem": w.problem,
+                   "n_systems": w.n, "t0": w.t0, "t1": w.t1, "rtol": w.rtol, "atol": w.atol,
+                   "ckpt_every": K, "gradients": "dL/dy0 [13] and dL/dlnA [27] per system",
+                   "systems_ok": int((ast.cpu().numpy() == 0).sum()),
+                   "mean_accepted_steps": n_steps / w.n, "max_stages": ms},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": dom, "kernel_ms": dom_ms,
+                     "algorithmic_flops_per_launch": dom_flops,
+                     "forward_ms": fwd_ms, "reverse_ms": rev_ms,
+                     "forward_flops": fwd_flops, "reverse_flops": rev_flops},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle adjoint on a sample")
+        from oracle import oracle as orc
+        pb = orc.network(net)
+        cores = orc.max_threads()
+
+        def run(m):
+            idx = np.unique(np.linspace(0, w.n - 1, m).astype(np.int64))
+            a = [np.ascontiguousarray(x[:, idx]) for x in (y0, g, wt)]
+            t = time.perf_counter()
+            orc.rkc_adjoint_batch(pb, a[0], a[1], a[2], w.t0, w.t1, w.rtol, w.atol)
+            return len(idx), time.perf_counter() - t
+
+        m, dt = run(min(w.n, max(64, 8 * cores)))
+        if dt < args.cpu_seconds and m < w.n:
+            m, dt = run(min(w.n, max(m, int(m * args.cpu_seconds / max(dt, 1e-6)))))
+        res["cpu_baseline"] = {"value": m / dt, "unit": "grads/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{m} of {w.n} systems (evenly spaced), {dt:.1f} s on "
+                                         f"{cores} threads, store-everything adjoint",
+                               "gpu_speedup": value / (m / dt)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="net13_rkc")
+    ap.add_argument("--n", type=int, default=0,
+                    help="systems (default: the workload's own count); for profiling runs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="auto", choices=["auto", "plain", "persistent"])
@@ -107,7 +217,13 @@ def main():
     from paper_1611_02274_amd import inputs as I
 
     w = I.WORKLOADS[args.workload]
+    if args.n > 0:
+        import dataclasses
+        w = dataclasses.replace(w, n=args.n)
     net = None if w.problem == "vdp" else I.network_of(w.problem)
+    if w.name.endswith("_adjoint"):
+        adjoint_bench(args, w, net)
+        return
     log(f"bench: workload {w.name} n={w.n}; generating inputs")
     y0, g = I.workload_inputs(w)
     dev = torch.device("cuda:0")

@@ -53,6 +53,8 @@ extern "C" {
 #define RK_SYS_NONFINITE 1    /* an accepted state was not finite */
 #define RK_SYS_HMIN 2         /* step fell below the minimum after a rejection */
 #define RK_SYS_MAXSTEPS 3     /* max_steps attempts used before reaching t1 */
+#define RK_SYS_TAPE 4         /* adjoint: the tape or workspace could not hold the system's
+                                 steps or stages; its gradients are NaN */
 
 /* Rows of the per-system statistics array. */
 #define RK_STAT_ACCEPT 0      /* accepted steps */
@@ -167,6 +169,129 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
                      const double *g, double t0, double t1, double rtol, double atol,
                      int32_t *status, int32_t *stats, void *ws, size_t ws_bytes,
                      const rk_options *opt, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of RKC (Sec. 2.2 stage recursion, transposed).
+ *
+ * The gradient is that of the map y(t0), theta -> y(t1) through the accepted
+ * steps, with every step size h_k and stage count s_k held at the values the
+ * controller chose; the controller, the spectral-radius estimates and the
+ * rejected attempts are not differentiated.  theta: the ln A_j of a
+ * mass-action network (both rate constants of reaction j scale with A_j), or
+ * mu for van der Pol.  Available for systems of up to 16 unknowns
+ * (RK_EUNSUPPORTED otherwise).
+ *
+ * A forward call records a tape (device memory the caller allocates): per
+ * system the accepted-step count, each accepted step's (h, s), and the state
+ * every ckpt_every accepted steps.  Layout, for n = n_sys, C = max_accepted,
+ * K = ckpt_every:
+ *   int32 count[n]          (-1: more than C accepted steps; no gradient)
+ *   double h[C][n], int32 s[C][n], double y[C / K + 1][N][n]
+ * each array starting on a 256-byte boundary.  The reverse call recomputes
+ * each segment of K steps from its checkpoint and each step's stages, and
+ * carries lambda = dL/dy(t1) back to dL/dy(t0).  The same n_sys, g,
+ * max_accepted and ckpt_every must be passed to both calls.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of a tape for n_sys systems of at most max_accepted accepted steps,
+ * with a checkpoint every ckpt_every accepted steps (0 on bad arguments). */
+size_t rk_tape_bytes(rk_problem p, int64_t n_sys, int64_t max_accepted, int32_t ckpt_every);
+
+/* RKC integration as rk_integrate_rkc (one lane per system), recording the
+ * tape.  tape: device memory of at least rk_tape_bytes(...) bytes, 256-byte
+ * aligned.  A system with more accepted steps than max_accepted integrates
+ * normally but its tape count is -1. */
+int rk_integrate_rkc_taped(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                           const double *g, double t0, double t1, double rtol, double atol,
+                           int32_t *status, int32_t *stats, void *tape, size_t tape_bytes,
+                           int64_t max_accepted, int32_t ckpt_every, const rk_options *opt,
+                           void *stream);
+
+/* Workspace bytes of rk_adjoint_rkc: per system max_stages stage records of
+ * N + 4 doubles and ckpt_every states (0 on bad arguments).  max_stages bounds
+ * the recorded stage counts (RK_STAT_MAX_STAGES of the forward call). */
+size_t rk_adjoint_workspace_bytes(rk_problem p, int64_t n_sys, int32_t max_stages,
+                                  int32_t ckpt_every);
+
+/* Reverse sweep over a tape from rk_integrate_rkc_taped:
+ *   dL_dy1    [N][n_sys]        lambda at t1 (for L = sum w . y(t1): w)
+ *   dL_dy0    [N][n_sys]        out: dL/dy(t0)
+ *   dL_dtheta [n_theta][n_sys]  out (or NULL): per-system dL/dtheta; for the
+ *                               network's shared ln A, sum over systems
+ *   status    [n_sys] or NULL   out: RK_SYS_OK, or RK_SYS_TAPE (NaN gradients)
+ *   ws, ws_bytes: at least rk_adjoint_workspace_bytes(...) bytes.
+ * Asynchronous on `stream`; argument errors are returned before anything is
+ * enqueued. */
+int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double *g, const void *tape,
+                   size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
+                   int32_t max_stages, const double *dL_dy1, double *dL_dy0,
+                   double *dL_dtheta, int32_t *status, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches: the systems of several compiled networks of different sizes
+ * (each network's systems in their own [N][n] block), integrated with RKC over
+ * operator-splitting substeps [t0 + k dt, t0 + (k + 1) dt], k < n_substeps,
+ * each substep a restart (Sec. 3), the state updated in place.
+ *
+ * RK_BATCH_PERSISTENT: one persistent launch per substep for all networks.
+ *   Every wave takes the networks in `order` and drains each network's
+ *   device queue in turn; lanes freed by finished systems take the next ones
+ *   (refill threshold per network), so a wave's live lanes stay packed and
+ *   one code path runs per wave.
+ * RK_BATCH_PLAIN_INTERLEAVED: one plain launch per substep over n_total
+ *   interleaved slots; slot i integrates system (slot_map[i] & 0x0fffffff) of
+ *   problem slot_map[i] >> 28, each lane running its own network's code.
+ * RK_BATCH_PLAIN_PER_NETWORK: one plain launch per network per substep.
+ * use_graph: the substeps are captured once into a HIP graph, replayed while
+ *   the call's arguments are unchanged.
+ * ------------------------------------------------------------------------- */
+typedef struct rk_batch_s *rk_batch;
+
+#define RK_BATCH_PERSISTENT 0
+#define RK_BATCH_PLAIN_INTERLEAVED 1
+#define RK_BATCH_PLAIN_PER_NETWORK 2
+
+typedef struct {
+  int32_t mode;          /* RK_BATCH_* */
+  int32_t waves_per_cu;  /* persistent grid: workgroups per compute unit; 0 = occupancy limit */
+  int32_t order[4];      /* persistent: problem indices in the order waves take them;
+                            order[0] < 0 = largest networks first */
+  int32_t refill[4];     /* persistent: idle lanes that trigger a refill, per problem; 0 = 16 */
+  int32_t use_graph;     /* nonzero: capture the substeps in one HIP graph */
+  int32_t reserved[4];   /* must be zero */
+} rk_batch_schedule;
+
+/* A batch over n_prob (1..4) network problems, given in the order every array
+ * argument of the batch calls follows.  The set of topologies must have been
+ * compiled into the library as a batch (RK_EUNSUPPORTED otherwise). */
+int rk_batch_create(const rk_problem *probs, int32_t n_prob, rk_batch *out);
+
+/* Releases the batch and its captured graph (not its problems).  No call using
+ * it may still be pending. */
+void rk_batch_destroy(rk_batch b);
+
+/* Device workspace bytes of rk_batch_integrate_rkc for n_sys[k] systems per
+ * problem (n_total: their sum, used by the interleaved form) under *sched
+ * (NULL = persistent, defaults) on the current device; 0 on bad arguments. */
+size_t rk_batch_workspace_bytes(rk_batch b, const int64_t *n_sys, int64_t n_total,
+                                const rk_batch_schedule *sched);
+
+/* Integrates every system of the batch over n_substeps substeps of dt from t0.
+ *   n_sys[k]            systems of problem k
+ *   y[k]                [N_k][n_sys[k]] device, updated in place
+ *   g[k]                [2][n_sys[k]] device (T, rho)
+ *   status[k], stats[k] device [n_sys[k]] / [RK_NSTATS][n_sys[k]], or a NULL
+ *                       array; values of the last substep
+ *   slot_map, n_total   interleaved form only (else NULL, 0)
+ *   ws, ws_bytes        at least rk_batch_workspace_bytes(...), 256-byte aligned
+ * Asynchronous on `stream`.  Calls on one batch must not overlap. */
+int rk_batch_integrate_rkc(rk_batch b, const int64_t *n_sys, double *const *y,
+                           const double *const *g, int32_t *const *status,
+                           int32_t *const *stats, const int32_t *slot_map, int64_t n_total,
+                           double t0, double dt, int32_t n_substeps, double rtol, double atol,
+                           const rk_options *opt, const rk_batch_schedule *sched, void *ws,
+                           size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,7 @@ import ctypes as C
 
 from . import _lib
 from ._lib import (RK_METHOD_RKC, RK_METHOD_RKCK, RK_NSTATS, RK_SYS_HMIN, RK_SYS_MAXSTEPS,
-                   RK_SYS_NONFINITE, RK_SYS_OK, RKError)
+                   RK_SYS_NONFINITE, RK_SYS_OK, RK_SYS_TAPE, RKError)
 
 STAT_ACCEPT, STAT_REJECT, STAT_RHS, STAT_SR_CALLS, STAT_POW_ITERS, STAT_MAX_STAGES = range(6)
 
@@ -140,6 +140,247 @@ def integrate_rkck(problem, y0, g, t0, t1, rtol, atol, **kw):
 def integrate_rkc(problem, y0, g, t0, t1, rtol, atol, **kw):
     """RKC integration (Sec. 2.2, Sec. 3.2, Appendix).  Returns (y1, status, stats)."""
     return _integrate(RK_METHOD_RKC, problem, y0, g, t0, t1, rtol, atol, **kw)
+
+
+class Tape:
+    """Device tape of an RKC integration (accepted steps' h and s, and the state
+    every ckpt_every accepted steps) for the discrete adjoint."""
+
+    def __init__(self, buf, n, max_accepted, ckpt_every, stats):
+        self.buf, self.n = buf, n
+        self.max_accepted, self.ckpt_every = max_accepted, ckpt_every
+        self.stats = stats
+
+    def _offsets(self):
+        def a256(x):
+            return (x + 255) // 256 * 256
+        n, cap = self.n, self.max_accepted
+        off_h = a256(4 * n)
+        off_s = off_h + a256(8 * cap * n)
+        return off_h, off_s
+
+    @property
+    def count(self):
+        """Accepted steps recorded per system (-1: more than max_accepted)."""
+        import torch
+        return self.buf[:4 * self.n].view(torch.int32)
+
+    @property
+    def h(self):
+        """[max_accepted, n] step sizes (rows beyond a system's count unused)."""
+        import torch
+        off_h, _ = self._offsets()
+        n, cap = self.n, self.max_accepted
+        return self.buf[off_h:off_h + 8 * cap * n].view(torch.float64).view(cap, n)
+
+    @property
+    def s(self):
+        """[max_accepted, n] stage counts (rows beyond a system's count unused)."""
+        import torch
+        _, off_s = self._offsets()
+        n, cap = self.n, self.max_accepted
+        return self.buf[off_s:off_s + 4 * cap * n].view(torch.int32).view(cap, n)
+
+
+def integrate_rkc_taped(problem, y0, g, t0, t1, rtol, atol, max_accepted=4096, ckpt_every=16,
+                        out=None, status=None, stats=None, stream=None, **opts):
+    """RKC integration that also records the tape of the discrete adjoint.
+    Returns (y1, status, stats, tape)."""
+    import torch
+    if y0.dim() != 2:
+        raise ValueError("y0 must be [N, n]")
+    n = y0.shape[1]
+    _check_tensor(y0, "y0", problem.n_eq, n, torch.float64)
+    dev = y0.device
+    if problem.n_param:
+        _check_tensor(g, "g", problem.n_param, n, torch.float64)
+    out = torch.empty_like(y0) if out is None else out
+    _check_tensor(out, "out", problem.n_eq, n, torch.float64)
+    status = torch.empty(n, dtype=torch.int32, device=dev) if status is None else status
+    stats = torch.empty((RK_NSTATS, n), dtype=torch.int32, device=dev) if stats is None else stats
+    opt = _options(**opts)
+    optp = C.byref(opt) if opt is not None else None
+    L = _lib.lib()
+    nb = L.rk_tape_bytes(problem.handle, n, int(max_accepted), int(ckpt_every))
+    if nb == 0 and n > 0:
+        raise ValueError("bad tape arguments")
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        buf = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        _lib.check(L.rk_integrate_rkc_taped(
+            problem.handle, n, y0.data_ptr(), out.data_ptr(),
+            g.data_ptr() if problem.n_param else None, float(t0), float(t1), float(rtol),
+            float(atol), status.data_ptr(), stats.data_ptr(), buf.data_ptr(), nb,
+            int(max_accepted), int(ckpt_every), optp, s.cuda_stream))
+    return out, status, stats, Tape(buf, n, int(max_accepted), int(ckpt_every), stats)
+
+
+def adjoint_rkc(problem, g, tape, dL_dy1, max_stages=None, stream=None):
+    """Reverse sweep of the discrete RKC adjoint over `tape`.  Returns
+    (dL/dy0 [N, n], per-system dL/dtheta [n_theta, n], status [n])."""
+    import torch
+    n = tape.n
+    _check_tensor(dL_dy1, "dL_dy1", problem.n_eq, n, torch.float64)
+    dev = dL_dy1.device
+    if max_stages is None:
+        max_stages = max(2, int(tape.stats[STAT_MAX_STAGES].max().item())) if n else 2
+    L = _lib.lib()
+    dy0 = torch.empty_like(dL_dy1)
+    dth = torch.empty((max(problem.n_theta, 1), n), dtype=torch.float64, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    nws = L.rk_adjoint_workspace_bytes(problem.handle, n, int(max_stages), tape.ckpt_every)
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+        _lib.check(L.rk_adjoint_rkc(problem.handle, n, g.data_ptr() if problem.n_param else None,
+                                    tape.buf.data_ptr(), tape.buf.numel(), tape.max_accepted,
+                                    tape.ckpt_every, int(max_stages), dL_dy1.data_ptr(),
+                                    dy0.data_ptr(), dth.data_ptr(), st.data_ptr(), ws.data_ptr(),
+                                    nws, s.cuda_stream))
+    return dy0, dth[:problem.n_theta], st
+
+
+def _autograd_function():
+    import torch
+
+    class RKCAdjoint(torch.autograd.Function):
+        """y1 = RKC(y0; theta) with the discrete adjoint as its backward.
+        Inputs: y0 [N, n]; g [P, n] (for van der Pol its row 0, mu, is the
+        differentiable parameter); lnA [n_rx] or None (networks: the shared
+        ln A_j, whose gradient sums the per-system contributions)."""
+
+        @staticmethod
+        def forward(ctx, y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted, ckpt_every):
+            while True:
+                y1, status, stats, tape = integrate_rkc_taped(
+                    problem, y0.detach(), g.detach() if g is not None else None, t0, t1, rtol,
+                    atol, max_accepted=max_accepted, ckpt_every=ckpt_every)
+                if int(tape.count.min().item()) >= 0 or y0.shape[1] == 0:
+                    break
+                max_accepted *= 2       # a system outran the tape: record again, longer
+            ctx.problem, ctx.tape, ctx.has_lnA = problem, tape, lnA is not None
+            ctx.save_for_backward(g)
+            ctx.mark_non_differentiable(status, stats)
+            return y1, status, stats
+
+        @staticmethod
+        def backward(ctx, gy1, _gst, _gstats):
+            (g,) = ctx.saved_tensors
+            dy0, dth, st = adjoint_rkc(ctx.problem, g, ctx.tape, gy1.contiguous())
+            dg = dlnA = None
+            if ctx.problem.kind == "vdp" and ctx.needs_input_grad[1]:
+                dg = dth
+            if ctx.has_lnA and ctx.needs_input_grad[2]:
+                dlnA = dth.sum(1)
+            return dy0, dg, dlnA, None, None, None, None, None, None, None
+
+    return RKCAdjoint
+
+
+_RKCAdjoint = None
+_lnA_problems = {}
+
+
+def rkc_solve(problem, y0, g, t0, t1, rtol, atol, lnA=None, max_accepted=4096, ckpt_every=16):
+    """Differentiable RKC integration: returns (y1, status, stats) with y1 in the
+    autograd graph of y0, g (van der Pol: mu) and lnA (networks, [n_rx]; the
+    problem's own values when None).  The backward pass is the discrete
+    adjoint, checkpointed every ckpt_every accepted steps."""
+    global _RKCAdjoint
+    if _RKCAdjoint is None:
+        _RKCAdjoint = _autograd_function()
+    if lnA is not None:
+        import dataclasses
+
+        import numpy as np
+        if problem.net is None:
+            raise ValueError("lnA applies to mass-action networks")
+        vals = np.ascontiguousarray(lnA.detach().cpu().numpy(), dtype=np.float64)
+        if vals.shape != (problem.net.n_rx,):
+            raise ValueError(f"lnA must have shape ({problem.net.n_rx},)")
+        if not np.array_equal(vals, problem.net.lnA):
+            key = (id(problem), vals.tobytes())
+            if key not in _lnA_problems:
+                _lnA_problems.clear()
+                _lnA_problems[key] = Problem.network(dataclasses.replace(problem.net, lnA=vals))
+            problem = _lnA_problems[key]
+    return _RKCAdjoint.apply(y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted, ckpt_every)
+
+
+class Batch:
+    """Ragged batch over several compiled networks (rk_batch_* in the C ABI):
+    RKC over operator-splitting substeps, each a restart, state in place."""
+
+    MODES = {"persistent": _lib.RK_BATCH_PERSISTENT,
+             "interleaved": _lib.RK_BATCH_PLAIN_INTERLEAVED,
+             "per_network": _lib.RK_BATCH_PLAIN_PER_NETWORK}
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p.handle.value if hasattr(p.handle, "value")
+                                                  else p.handle for p in self.problems])
+        h = C.c_void_p()
+        _lib.check(_lib.lib().rk_batch_create(arr, len(self.problems), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None and _lib._lib is not None:
+            _lib._lib.rk_batch_destroy(h)
+
+    @classmethod
+    def schedule(cls, mode="persistent", waves_per_cu=0, order=None, refill=None,
+                 use_graph=False):
+        s = _lib.BatchSchedule()
+        s.mode = cls.MODES[mode]
+        s.waves_per_cu = int(waves_per_cu)
+        for k in range(4):
+            s.order[k] = int(order[k]) if order is not None and k < len(order) else -1
+            s.refill[k] = int(refill[k]) if refill is not None and k < len(refill) else 0
+        s.use_graph = int(bool(use_graph))
+        return s
+
+    def integrate_rkc(self, ys, gs, t0, dt, n_substeps, rtol, atol, mode="persistent",
+                      waves_per_cu=0, order=None, refill=None, use_graph=False, slot_map=None,
+                      status=None, stats=None, stream=None, max_steps=None):
+        """ys[k] [N_k, n_k] and gs[k] [2, n_k] float64 CUDA tensors per problem,
+        integrated in place; status / stats: lists of tensors or None."""
+        import torch
+        m = len(self.problems)
+        if len(ys) != m or len(gs) != m:
+            raise ValueError("one y and one g per problem")
+        n = [int(y.shape[1]) for y in ys]
+        for k, (p, y, g) in enumerate(zip(self.problems, ys, gs)):
+            _check_tensor(y, f"ys[{k}]", p.n_eq, n[k], torch.float64)
+            _check_tensor(g, f"gs[{k}]", p.n_param, n[k], torch.float64)
+        dev = ys[0].device
+        sched = self.schedule(mode, waves_per_cu, order, refill, use_graph)
+        n_total = sum(n) if mode == "interleaved" else 0
+        if mode == "interleaved":
+            _check_tensor(slot_map, "slot_map", None, n_total, torch.int32)
+        nn = (C.c_int64 * m)(*n)
+        L = _lib.lib()
+        nws = L.rk_batch_workspace_bytes(self._h, nn, n_total, C.byref(sched))
+        if nws == 0 and sum(n) > 0:
+            raise RKError(_lib.RK_EINVAL, L.rk_last_error().decode())
+
+        def ptrs(ts):
+            return None if ts is None else (C.c_void_p * m)(*[t.data_ptr() for t in ts])
+
+        opt = _options(max_steps=max_steps)
+        with torch.cuda.device(dev):
+            s = stream if stream is not None else torch.cuda.current_stream(dev)
+            ws = getattr(self, "_ws", None)
+            if ws is None or ws.numel() < nws or ws.device != dev:
+                # one workspace per batch, reused: a captured graph refers to it
+                ws = self._ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+            _lib.check(L.rk_batch_integrate_rkc(
+                self._h, nn, ptrs(ys), ptrs(gs), ptrs(status), ptrs(stats),
+                slot_map.data_ptr() if mode == "interleaved" else None, n_total, float(t0),
+                float(dt), int(n_substeps), float(rtol), float(atol),
+                C.byref(opt) if opt is not None else None, C.byref(sched), ws.data_ptr(), nws,
+                s.cuda_stream))
+        return ys
 
 
 def version() -> int:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librkmi.so")
 
 RK_OK, RK_EINVAL, RK_ENOMEM, RK_EHIP, RK_EUNSUPPORTED, RK_EWORKSPACE = 0, -1, -2, -3, -4, -5
-RK_SYS_OK, RK_SYS_NONFINITE, RK_SYS_HMIN, RK_SYS_MAXSTEPS = 0, 1, 2, 3
+RK_SYS_OK, RK_SYS_NONFINITE, RK_SYS_HMIN, RK_SYS_MAXSTEPS, RK_SYS_TAPE = 0, 1, 2, 3, 4
 RK_NSTATS = 6
 RK_METHOD_RKCK, RK_METHOD_RKC = 0, 1
 
@@ -34,6 +34,14 @@ class MechDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("sr_period", C.c_int32), ("sr_itmax", C.c_int32),
                 ("schedule", C.c_int32), ("refill", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class BatchSchedule(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("waves_per_cu", C.c_int32), ("order", C.c_int32 * 4),
+                ("refill", C.c_int32 * 4), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+RK_BATCH_PERSISTENT, RK_BATCH_PLAIN_INTERLEAVED, RK_BATCH_PLAIN_PER_NETWORK = 0, 1, 2
 
 
 class RKError(RuntimeError):
@@ -67,6 +75,29 @@ def lib():
         for name in ("rk_integrate_rkck", "rk_integrate_rkc"):
             getattr(L, name).argtypes = integ
             getattr(L, name).restype = C.c_int
+        L.rk_tape_bytes.argtypes = [vp, i64, i64, C.c_int32]
+        L.rk_tape_bytes.restype = C.c_size_t
+        L.rk_integrate_rkc_taped.argtypes = [vp, i64, dp, dp, dp, C.c_double, C.c_double,
+                                             C.c_double, C.c_double, vp, vp, vp, C.c_size_t,
+                                             i64, C.c_int32, C.POINTER(Options), vp]
+        L.rk_integrate_rkc_taped.restype = C.c_int
+        L.rk_adjoint_workspace_bytes.argtypes = [vp, i64, C.c_int32, C.c_int32]
+        L.rk_adjoint_workspace_bytes.restype = C.c_size_t
+        L.rk_adjoint_rkc.argtypes = [vp, i64, dp, vp, C.c_size_t, i64, C.c_int32, C.c_int32, dp,
+                                     dp, dp, vp, vp, C.c_size_t, vp]
+        L.rk_adjoint_rkc.restype = C.c_int
+        L.rk_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+        L.rk_batch_create.restype = C.c_int
+        L.rk_batch_destroy.argtypes = [vp]
+        L.rk_batch_destroy.restype = None
+        L.rk_batch_workspace_bytes.argtypes = [vp, C.POINTER(i64), i64, C.POINTER(BatchSchedule)]
+        L.rk_batch_workspace_bytes.restype = C.c_size_t
+        L.rk_batch_integrate_rkc.argtypes = [vp, C.POINTER(i64), C.POINTER(vp), C.POINTER(vp),
+                                             C.POINTER(vp), C.POINTER(vp), vp, i64, C.c_double,
+                                             C.c_double, C.c_int32, C.c_double, C.c_double,
+                                             C.POINTER(Options), C.POINTER(BatchSchedule),
+                                             vp, C.c_size_t, vp]
+        L.rk_batch_integrate_rkc.restype = C.c_int
         _lib = L
     return _lib
 

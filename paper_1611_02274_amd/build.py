@@ -22,6 +22,8 @@ ARCH = "gfx950"
 
 # Networks compiled into the library (species counts of the standard networks).
 COMPILED_NETWORKS = (9, 13, 32, 53)
+# Ragged batches compiled as one kernel (species counts, in order).
+COMPILED_BATCHES = ((9, 13, 32, 53),)
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -39,7 +41,8 @@ def sources():
     from .inputs import standard_network
     gen_crmath.generate()
     nets = [standard_network(k) for k in COMPILED_NETWORKS]
-    gen = codegen.generate(nets)
+    batches = [[standard_network(k) for k in b] for b in COMPILED_BATCHES]
+    gen = codegen.generate(nets, batches=batches)
     hand = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
     return hand + gen
 

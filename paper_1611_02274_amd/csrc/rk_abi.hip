@@ -9,18 +9,26 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rkmi.h"
-#include "rk_launch.hpp"
+#include "rk_adjoint.hpp"
+#include "rk_batch.hpp"
 
 extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s);
 extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a);
 extern "C" int64_t rkmi_vdp_workspace(int method, int schedule, int64_t n);
+extern "C" int rkmi_vdp_taped(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t, void* s);
+extern "C" int rkmi_vdp_taped_host(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t);
+extern "C" int rkmi_vdp_adjoint(const rkmi::AdjointArgs* a, void* s);
+extern "C" int rkmi_vdp_adjoint_host(const rkmi::AdjointArgs* a);
 
 namespace rkmi {
 extern const GenEntry kGenRegistry[];
 extern const int kGenRegistrySize;
+extern const BatchEntry kBatchRegistry[];
+extern const int kBatchRegistrySize;
 }  // namespace rkmi
 
 namespace {
@@ -50,6 +58,11 @@ struct rk_problem_s {
   rkmi::launch_fn launch = nullptr;
   rkmi::host_fn host = nullptr;
   rkmi::workspace_fn workspace = nullptr;
+  rkmi::taped_fn taped = nullptr;
+  rkmi::taped_host_fn taped_host = nullptr;
+  rkmi::adjoint_fn adjoint = nullptr;
+  rkmi::adjoint_host_fn adjoint_host = nullptr;
+  int gen_index = -1;                  // row of the network registry
   std::vector<double> host_prm;        // uniform problem data, device layout
   double* dev_prm[kMaxDevices] = {};   // per-device copies, made on first use
   std::mutex mu;
@@ -110,18 +123,9 @@ int check_device_ptr(const void* ptr, size_t align, const char* name, bool allow
   return RK_OK;
 }
 
-// Launch arguments and the launch-uniform controls of the drivers.
-void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, double* y1,
-               const double* g, double t0, double t1, double rtol, double atol, int32_t* status,
-               int32_t* stats, void* ws, size_t ws_bytes, const rk_options* opt) {
-  a.method = method;
-  a.schedule = opt ? opt->schedule : 0;
-  a.n = n;
-  a.y0 = y0;
-  a.y1 = y1;
-  a.g = g;
-  a.prm = nullptr;
-  rkmi::Ctl& c = a.ctl;
+// The launch-uniform controls of the drivers for [t0, t1].
+void fill_ctl(rkmi::Ctl& c, double t0, double t1, double rtol, double atol,
+              const rk_options* opt) {
   c.t0 = t0;
   c.t1 = t1;
   c.rtol = rtol;
@@ -137,6 +141,20 @@ void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, dou
   c.refill = (opt && opt->refill > 0) ? (opt->refill > rkmi::kLdsStride ? rkmi::kLdsStride
                                                                         : opt->refill)
                                       : rkmi::kDefaultRefill;
+}
+
+// Launch arguments and the launch-uniform controls of the drivers.
+void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, double* y1,
+               const double* g, double t0, double t1, double rtol, double atol, int32_t* status,
+               int32_t* stats, void* ws, size_t ws_bytes, const rk_options* opt) {
+  a.method = method;
+  a.schedule = opt ? opt->schedule : 0;
+  a.n = n;
+  a.y0 = y0;
+  a.y1 = y1;
+  a.g = g;
+  a.prm = nullptr;
+  fill_ctl(a.ctl, t0, t1, rtol, atol, opt);
   a.status = status;
   a.stats = stats;
   a.ws = ws;
@@ -145,9 +163,15 @@ void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, dou
 
 int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1, const double* g,
               double t0, double t1, double rtol, double atol, int32_t* status, int32_t* stats,
-              void* ws, size_t ws_bytes, const rk_options* opt, void* stream) {
+              void* ws, size_t ws_bytes, const rk_options* opt, void* stream,
+              const rkmi::TapeArgs* tape = nullptr) {
   g_err.clear();
   if (!p) return fail(RK_EINVAL, "problem handle is NULL");
+  if (tape && !p->taped)
+    return fail(RK_EUNSUPPORTED, "the adjoint is not compiled for this problem (systems of "
+                "more than 16 unknowns keep their vectors in workspace columns)");
+  if (tape && (tape->K < 1 || tape->cap < 0))
+    return fail(RK_EINVAL, "need ckpt_every >= 1 and max_accepted >= 0");
   if (n < 0) return fail(RK_EINVAL, "n_sys = %lld is negative", (long long)n);
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
     return fail(RK_EINVAL, "need finite t0 <= t1 (got %g, %g)", t0, t1);
@@ -167,8 +191,15 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if ((rc = check_device_ptr(status, 4, "status", true))) return rc;
   if ((rc = check_device_ptr(stats, 4, "stats", true))) return rc;
   if ((rc = check_device_ptr(ws, 8, "ws", true))) return rc;
+  if (tape) {
+    if ((rc = check_device_ptr(tape->tape, 256, "tape", false))) return rc;
+    const size_t need = rkmi::tape_layout(n, tape->cap, tape->K, p->n_eq).bytes;
+    if (tape->tape_bytes < need)
+      return fail(RK_EWORKSPACE, "tape of %zu bytes is too small (%zu needed)", tape->tape_bytes,
+                  need);
+  }
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  if (t1 == t0) {
+  if (t1 == t0 && !tape) {
     // nothing to integrate: copy the state, zero status and statistics (a
     // kernel rather than memset/memcpy nodes, so the call is graph-capturable)
     const int64_t blocks = (n + 255) / 256;
@@ -180,7 +211,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
   if ((rc = problem_device_data(p, &a.prm))) return rc;
-  rc = p->launch(&a, stream);
+  rc = tape ? p->taped(&a, tape, stream) : p->launch(&a, stream);
   if (rc == rkmi::kLaunchWorkspace)
     return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (rk_workspace_bytes gives "
                 "the size this call needs)", ws ? ws_bytes : (size_t)0);
@@ -210,6 +241,10 @@ int rk_problem_create_vdp(rk_problem* out) {
   p->launch = rkmi_vdp_launch;
   p->host = rkmi_vdp_host;
   p->workspace = rkmi_vdp_workspace;
+  p->taped = rkmi_vdp_taped;
+  p->taped_host = rkmi_vdp_taped_host;
+  p->adjoint = rkmi_vdp_adjoint;
+  p->adjoint_host = rkmi_vdp_adjoint_host;
   *out = p;
   return RK_OK;
 }
@@ -238,12 +273,14 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
     if (!(d->W[k] > 0.0) || !std::isfinite(d->W[k]))
       return fail(RK_EINVAL, "species %d has invalid molar mass", k);
   const rkmi::GenEntry* hit = nullptr;
+  int hit_index = -1;
   for (int e = 0; e < rkmi::kGenRegistrySize; ++e) {
     const rkmi::GenEntry& E = rkmi::kGenRegistry[e];
     if (E.n_sp == d->n_sp && E.n_rx == d->n_rx &&
         !std::memcmp(E.reac, d->reac, sizeof(int32_t) * 2 * d->n_rx) &&
         !std::memcmp(E.prod, d->prod, sizeof(int32_t) * 2 * d->n_rx)) {
       hit = &E;
+      hit_index = e;
       break;
     }
   }
@@ -262,6 +299,11 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
   p->launch = hit->launch;
   p->host = hit->host;
   p->workspace = hit->workspace;
+  p->taped = hit->taped;
+  p->taped_host = hit->taped_host;
+  p->adjoint = hit->adjoint;
+  p->adjoint_host = hit->adjoint_host;
+  p->gen_index = hit_index;
   const int nr = d->n_rx, ns = d->n_sp;
   p->host_prm.resize(4 * nr + 2 * ns);
   for (int j = 0; j < nr; ++j) {
@@ -331,6 +373,262 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double* y0, double* y1, 
                    ws_bytes, opt, stream);
 }
 
+size_t rk_tape_bytes(rk_problem p, int64_t n_sys, int64_t max_accepted, int32_t ckpt_every) {
+  g_err.clear();
+  if (!p || n_sys < 0 || max_accepted < 0 || ckpt_every < 1) return 0;
+  return rkmi::tape_layout(n_sys, max_accepted, ckpt_every, p->n_eq).bytes;
+}
+
+int rk_integrate_rkc_taped(rk_problem p, int64_t n_sys, const double* y0, double* y1,
+                           const double* g, double t0, double t1, double rtol, double atol,
+                           int32_t* status, int32_t* stats, void* tape, size_t tape_bytes,
+                           int64_t max_accepted, int32_t ckpt_every, const rk_options* opt,
+                           void* stream) {
+  const rkmi::TapeArgs t{tape, tape_bytes, max_accepted, ckpt_every};
+  return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats,
+                   nullptr, 0, opt, stream, &t);
+}
+
+size_t rk_adjoint_workspace_bytes(rk_problem p, int64_t n_sys, int32_t max_stages,
+                                  int32_t ckpt_every) {
+  g_err.clear();
+  if (!p || n_sys <= 0 || max_stages < 2 || ckpt_every < 1) return 0;
+  const int64_t blocks = (n_sys + rkmi::kLdsStride - 1) / rkmi::kLdsStride;
+  const int64_t rows = (int64_t)max_stages * (p->n_eq + 4) + (int64_t)ckpt_every * p->n_eq;
+  return (size_t)(blocks * rows * rkmi::kLdsStride * (int64_t)sizeof(double));
+}
+
+int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double* g, const void* tape,
+                   size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
+                   int32_t max_stages, const double* dL_dy1, double* dL_dy0, double* dL_dtheta,
+                   int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!p) return fail(RK_EINVAL, "problem handle is NULL");
+  if (!p->adjoint)
+    return fail(RK_EUNSUPPORTED, "the adjoint is not compiled for this problem (systems of "
+                "more than 16 unknowns keep their vectors in workspace columns)");
+  if (n_sys < 0) return fail(RK_EINVAL, "n_sys = %lld is negative", (long long)n_sys);
+  if (ckpt_every < 1 || max_accepted < 0 || max_stages < 2)
+    return fail(RK_EINVAL, "need ckpt_every >= 1, max_accepted >= 0 and max_stages >= 2");
+  if (n_sys == 0) return RK_OK;
+  int rc;
+  if ((rc = check_device_ptr(g, 8, "g", p->n_param == 0))) return rc;
+  if ((rc = check_device_ptr(tape, 256, "tape", false))) return rc;
+  if ((rc = check_device_ptr(dL_dy1, 8, "dL_dy1", false))) return rc;
+  if ((rc = check_device_ptr(dL_dy0, 8, "dL_dy0", false))) return rc;
+  if ((rc = check_device_ptr(dL_dtheta, 8, "dL_dtheta", true))) return rc;
+  if ((rc = check_device_ptr(status, 4, "status", true))) return rc;
+  if ((rc = check_device_ptr(ws, 8, "ws", false))) return rc;
+  const size_t tneed = rkmi::tape_layout(n_sys, max_accepted, ckpt_every, p->n_eq).bytes;
+  if (tape_bytes < tneed)
+    return fail(RK_EINVAL, "tape of %zu bytes is smaller than its layout (%zu)", tape_bytes, tneed);
+  const size_t wneed = rk_adjoint_workspace_bytes(p, n_sys, max_stages, ckpt_every);
+  if (ws_bytes < wneed)
+    return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (%zu needed)", ws_bytes, wneed);
+  rkmi::AdjointArgs a{};
+  a.n = n_sys;
+  a.g = g;
+  a.tape = rkmi::TapeArgs{const_cast<void*>(tape), tape_bytes, max_accepted, ckpt_every};
+  a.max_stages = max_stages;
+  a.w = dL_dy1;
+  a.dy0 = dL_dy0;
+  a.dth = dL_dtheta;
+  a.status = status;
+  a.ws = ws;
+  a.ws_bytes = ws_bytes;
+  if ((rc = problem_device_data(p, &a.prm))) return rc;
+  rc = p->adjoint(&a, stream);
+  if (rc) return fail(RK_EHIP, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return RK_OK;
+}
+
+struct rk_batch_s {
+  const rkmi::BatchEntry* entry = nullptr;
+  rk_problem probs[rkmi::kBatchMaxNets] = {};  // in the caller's order
+  int user_to_entry[rkmi::kBatchMaxNets] = {};
+  int n = 0;
+  void* graph_cache = nullptr;
+  std::mutex mu;
+};
+
+int rk_batch_create(const rk_problem* probs, int32_t n_prob, rk_batch* out) {
+  g_err.clear();
+  if (!out) return fail(RK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!probs || n_prob < 1 || n_prob > rkmi::kBatchMaxNets)
+    return fail(RK_EINVAL, "need 1..%d problems", rkmi::kBatchMaxNets);
+  for (int k = 0; k < n_prob; ++k)
+    if (!probs[k] || probs[k]->gen_index < 0)
+      return fail(RK_EINVAL, "problem %d is not a compiled mass-action network", k);
+  for (int e = 0; e < rkmi::kBatchRegistrySize; ++e) {
+    const rkmi::BatchEntry& E = rkmi::kBatchRegistry[e];
+    if (E.n_net != n_prob || !E.launch) continue;
+    int map[rkmi::kBatchMaxNets];
+    bool used[rkmi::kBatchMaxNets] = {};
+    bool ok = true;
+    for (int k = 0; k < n_prob && ok; ++k) {
+      map[k] = -1;
+      for (int j = 0; j < E.n_net; ++j)
+        if (!used[j] && E.gen_index[j] == probs[k]->gen_index) {
+          map[k] = j;
+          used[j] = true;
+          break;
+        }
+      ok = map[k] >= 0;
+    }
+    if (!ok) continue;
+    rk_batch b = new (std::nothrow) rk_batch_s();
+    if (!b) return fail(RK_ENOMEM, "out of host memory");
+    b->entry = &E;
+    b->n = n_prob;
+    for (int k = 0; k < n_prob; ++k) {
+      b->probs[k] = probs[k];
+      b->user_to_entry[k] = map[k];
+    }
+    b->graph_cache = new (std::nothrow) rkmi::BatchGraphCache();
+    if (!b->graph_cache) {
+      delete b;
+      return fail(RK_ENOMEM, "out of host memory");
+    }
+    *out = b;
+    return RK_OK;
+  }
+  return fail(RK_EUNSUPPORTED, "no batch kernel is compiled for this set of networks");
+}
+
+void rk_batch_destroy(rk_batch b) {
+  if (!b) return;
+  if (b->graph_cache) b->entry->free_cache(b->graph_cache);
+  delete b;
+}
+
+namespace {
+
+// Fills the batch arguments in the compiled network order.
+int batch_args(rk_batch b, const int64_t* n_sys, double* const* y, const double* const* g,
+               int32_t* const* status, int32_t* const* stats, const int32_t* map, int64_t n_total,
+               double t0, double dt, int32_t n_substeps, double rtol, double atol,
+               const rk_options* opt, const rk_batch_schedule* sched, void* ws, size_t ws_bytes,
+               bool with_pointers, rkmi::BatchArgs& a) {
+  a = rkmi::BatchArgs{};
+  a.mode = sched ? sched->mode : RK_BATCH_PERSISTENT;
+  if (a.mode < RK_BATCH_PERSISTENT || a.mode > RK_BATCH_PLAIN_PER_NETWORK)
+    return fail(RK_EUNSUPPORTED, "batch mode %d is not available", a.mode);
+  if (sched)
+    for (int k = 0; k < 4; ++k)
+      if (sched->reserved[k]) return fail(RK_EINVAL, "rk_batch_schedule.reserved must be zero");
+  a.n_net = b->n;
+  a.waves_per_cu = sched ? sched->waves_per_cu : 0;
+  a.use_graph = sched ? sched->use_graph : 0;
+  for (int k = 0; k < rkmi::kBatchMaxNets; ++k) a.order[k] = k, a.map_net[k] = 0;
+  for (int k = 0; k < b->n; ++k) {
+    const int e = b->user_to_entry[k];
+    if (n_sys[k] < 0 || n_sys[k] > 0x0fffffff)
+      return fail(RK_EINVAL, "n_sys[%d] = %lld out of range", k, (long long)n_sys[k]);
+    a.net[e].n = n_sys[k];
+    a.map_net[k] = e;
+    a.refill[e] = sched ? sched->refill[k] : 0;
+    if (with_pointers && n_sys[k] > 0) {
+      int rc;
+      if ((rc = check_device_ptr(y[k], 8, "y", false))) return rc;
+      if ((rc = check_device_ptr(g[k], 8, "g", false))) return rc;
+      if (status && (rc = check_device_ptr(status[k], 4, "status", true))) return rc;
+      if (stats && (rc = check_device_ptr(stats[k], 4, "stats", true))) return rc;
+      if ((rc = problem_device_data(b->probs[k], &a.net[e].prm))) return rc;
+      a.net[e].y = y[k];
+      a.net[e].g = g[k];
+      a.net[e].status = status ? status[k] : nullptr;
+      a.net[e].stats = stats ? stats[k] : nullptr;
+    }
+  }
+  // order: as given, else the largest networks first
+  bool given = sched && sched->order[0] >= 0;
+  if (given) {
+    bool seen[rkmi::kBatchMaxNets] = {};
+    for (int r = 0; r < b->n; ++r) {
+      const int k = sched->order[r];
+      if (k < 0 || k >= b->n || seen[k]) return fail(RK_EINVAL, "order is not a permutation");
+      seen[k] = true;
+      a.order[r] = b->user_to_entry[k];
+    }
+  } else {
+    int idx[rkmi::kBatchMaxNets];
+    for (int k = 0; k < b->n; ++k) idx[k] = k;
+    for (int i = 0; i < b->n; ++i)
+      for (int j = i + 1; j < b->n; ++j)
+        if (b->probs[idx[j]]->n_eq > b->probs[idx[i]]->n_eq) std::swap(idx[i], idx[j]);
+    for (int r = 0; r < b->n; ++r) a.order[r] = b->user_to_entry[idx[r]];
+  }
+  a.map = map;
+  a.n_total = n_total;
+  if (a.mode == RK_BATCH_PLAIN_INTERLEAVED) {
+    int64_t tot = 0;
+    for (int k = 0; k < b->n; ++k) tot += n_sys[k];
+    if (n_total != tot) return fail(RK_EINVAL, "n_total must be the sum of n_sys");
+    if (with_pointers && n_total > 0) {
+      int rc;
+      if ((rc = check_device_ptr(map, 4, "slot_map", false))) return rc;
+    }
+  }
+  if (!std::isfinite(t0) || !std::isfinite(dt) || !(dt > 0.0) || n_substeps < 0)
+    return fail(RK_EINVAL, "need finite t0, dt > 0 and n_substeps >= 0");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(RK_EINVAL, "rtol must be positive");
+  if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(RK_EINVAL, "atol must be >= 0");
+  fill_ctl(a.ctl, t0, t0 + dt, rtol, atol, opt);
+  a.t0 = t0;
+  a.dt = dt;
+  a.n_substeps = n_substeps;
+  a.ws = ws;
+  a.ws_bytes = ws_bytes;
+  a.graph_cache = b->graph_cache;
+  return RK_OK;
+}
+
+}  // namespace
+
+size_t rk_batch_workspace_bytes(rk_batch b, const int64_t* n_sys, int64_t n_total,
+                                const rk_batch_schedule* sched) {
+  g_err.clear();
+  if (!b || !n_sys) return 0;
+  rkmi::BatchArgs a;
+  if (batch_args(b, n_sys, nullptr, nullptr, nullptr, nullptr, nullptr, n_total, 0.0, 1.0, 1,
+                 1e-6, 0.0, nullptr, sched, nullptr, 0, false, a))
+    return 0;
+  const int64_t need = b->entry->workspace(&a);
+  if (need < 0) {
+    fail(RK_EHIP, "could not query the current device");
+    return 0;
+  }
+  return (size_t)need;
+}
+
+int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
+                           const double* const* g, int32_t* const* status, int32_t* const* stats,
+                           const int32_t* slot_map, int64_t n_total, double t0, double dt,
+                           int32_t n_substeps, double rtol, double atol, const rk_options* opt,
+                           const rk_batch_schedule* sched, void* ws, size_t ws_bytes,
+                           void* stream) {
+  g_err.clear();
+  if (!b) return fail(RK_EINVAL, "batch handle is NULL");
+  if (!n_sys || !y || !g) return fail(RK_EINVAL, "n_sys, y and g are required");
+  if (opt)
+    for (int k = 0; k < 6; ++k)
+      if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
+  rkmi::BatchArgs a;
+  int rc = batch_args(b, n_sys, y, g, status, stats, slot_map, n_total, t0, dt, n_substeps, rtol,
+                      atol, opt, sched, ws, ws_bytes, true, a);
+  if (rc) return rc;
+  if ((rc = check_device_ptr(ws, 256, "ws", true))) return rc;
+  std::lock_guard<std::mutex> lock(b->mu);
+  rc = b->entry->launch(&a, stream);
+  if (rc == rkmi::kLaunchWorkspace)
+    return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (rk_batch_workspace_bytes "
+                "gives the size this call needs)", ws ? ws_bytes : (size_t)0);
+  if (rc == rkmi::kLaunchInvalid) return fail(RK_EINVAL, "too many systems for one launch");
+  if (rc) return fail(RK_EHIP, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return RK_OK;
+}
+
 // Test hook, not part of the public ABI: runs the kernels' per-system code on
 // the host over HOST arrays, so the CPU test suite can compare the kernels'
 // arithmetic with the reference bit for bit.  Integration calls never use it.
@@ -347,6 +645,41 @@ int rkmi_test_host_integrate(int32_t method, rk_problem p, int64_t n, const doub
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0, &o);
   a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
   return p->host(&a);
+}
+
+// Test hooks, not part of the public ABI: the taped forward and the adjoint's
+// per-system code run on the host over HOST arrays (tape and workspace too).
+int rkmi_test_host_taped(rk_problem p, int64_t n, const double* y0, double* y1, const double* g,
+                         double t0, double t1, double rtol, double atol, int32_t* status,
+                         int32_t* stats, void* tape, size_t tape_bytes, int64_t cap, int32_t K) {
+  g_err.clear();
+  if (!p || !p->taped_host || n < 0 || !y0 || !y1 || (p->n_param && !g) || !(t1 >= t0) ||
+      !(rtol > 0.0) || !(atol >= 0.0) || !tape || K < 1 || cap < 0)
+    return fail(RK_EINVAL, "invalid arguments");
+  rkmi::LaunchArgs a;
+  fill_args(a, rkmi::kMethodRkc, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0,
+            nullptr);
+  a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
+  const rkmi::TapeArgs t{tape, tape_bytes, cap, K};
+  return p->taped_host(&a, &t);
+}
+
+int rkmi_test_host_adjoint(rk_problem p, int64_t n, const double* g, void* tape,
+                           size_t tape_bytes, int64_t cap, int32_t K, int32_t max_stages,
+                           const double* w, double* dy0, double* dth, int32_t* status) {
+  g_err.clear();
+  if (!p || !p->adjoint_host || n < 0 || !tape || !w || !dy0) return fail(RK_EINVAL, "invalid arguments");
+  rkmi::AdjointArgs a{};
+  a.n = n;
+  a.g = g;
+  a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
+  a.tape = rkmi::TapeArgs{tape, tape_bytes, cap, K};
+  a.max_stages = max_stages;
+  a.w = w;
+  a.dy0 = dy0;
+  a.dth = dth;
+  a.status = status;
+  return p->adjoint_host(&a);
 }
 
 }  // extern "C"

@@ -1,0 +1,360 @@
+// rk_adjoint.hpp -- discrete adjoint of the RKC step sequence.
+//
+// The gradient is that of the map from y(t0) (and the problem's parameters
+// theta) to y(t1) through the accepted steps, with each step's size h_k and
+// stage count s_k held at the values the controller chose (rejected attempts,
+// the controller and the spectral-radius estimates are not differentiated).
+// Sec. 2.2 stage recursion, transposed: for a loss L with lambda = dL/dy(t1),
+//   for j = s..2:  w0^ += (1 - mu_j - nu_j) wj^,  w_{j-1}^ += mu_j wj^,
+//                  w_{j-2}^ += nu_j wj^,  F0^ += gt_j h wj^,
+//                  u = mut_j h wj^:  w_{j-1}^ += J(w_{j-1})^T u,
+//                  theta^ += (df/dtheta)(w_{j-1})^T u;
+//   w0^ += w1^,  F0^ += mut_1 h w1^,  w0^ += J(w_0)^T F0^,
+//   theta^ += (df/dtheta)(w_0)^T F0^,  and lambda = w0^ for the step before.
+//
+// Forward: the ordinary RKC integration, recording every accepted step's
+// (h, s) and the state every K accepted steps (the tape).  Reverse: per
+// segment of K steps, last segment first, the step-start states are
+// recomputed from the segment's checkpoint; per step, last first, the stages
+// w_0..w_{s-1} and their coefficients are recomputed into the lane's columns
+// and the transposed recursion runs in registers.  One lane per system.
+#pragma once
+
+#include "rk_launch.hpp"
+
+namespace rkmi {
+
+enum : int32_t { kSysTape = 4 };
+
+// Tape layout for n systems, cap steps, period K, N unknowns:
+//   count int32 [n] | h double [cap][n] | s int32 [cap][n] | y double [cap/K + 1][N][n]
+struct TapeLayout {
+  size_t off_h, off_s, off_ckpt, bytes;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline TapeLayout tape_layout(int64_t n, int64_t cap, int32_t K, int N) {
+  TapeLayout t;
+  t.off_h = align256(sizeof(int32_t) * (size_t)n);
+  t.off_s = t.off_h + align256(sizeof(double) * (size_t)cap * (size_t)n);
+  t.off_ckpt = t.off_s + align256(sizeof(int32_t) * (size_t)cap * (size_t)n);
+  t.bytes = t.off_ckpt + sizeof(double) * (size_t)(cap / K + 1) * (size_t)N * (size_t)n;
+  return t;
+}
+
+struct TapeView {
+  int32_t* count;   // accepted steps per system, -1 when they exceeded cap
+  double* h;        // [cap][n]
+  int32_t* s;       // [cap][n]
+  double* ckpt;     // [cap/K + 1][N][n]
+  int64_t n, cap;
+  int32_t K;
+};
+
+inline TapeView tape_view(const TapeArgs& a, int64_t n, int N) {
+  const TapeLayout L = tape_layout(n, a.cap, a.K, N);
+  unsigned char* b = static_cast<unsigned char*>(a.tape);
+  return TapeView{reinterpret_cast<int32_t*>(b), reinterpret_cast<double*>(b + L.off_h),
+                  reinterpret_cast<int32_t*>(b + L.off_s),
+                  reinterpret_cast<double*>(b + L.off_ckpt), n, a.cap, a.K};
+}
+
+// Forward recorder of system i.
+template <int N>
+struct TapeRec {
+  TapeView T;
+  int64_t i;
+  bool full;
+  template <class V>
+  RKMI_HD void checkpoint(int64_t c, const V& y) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) T.ckpt[(c * N + k) * T.n + i] = y[k];
+  }
+  template <class V>
+  RKMI_HD void accept(double h, int m, const V& yn, int64_t nstep) {
+    const int64_t k = nstep - 1;
+    if (full || k >= T.cap) {
+      full = true;
+      return;
+    }
+    T.h[k * T.n + i] = h;
+    T.s[k * T.n + i] = m;
+    if (nstep % T.K == 0) checkpoint(nstep / T.K, yn);
+  }
+};
+
+// Stage records of one step in the lane's columns: record j (1..s) holds
+// w_{j-1} and (mu_j, nu_j, mut_j, gt_j); record 1 holds w_0 and mut_1.
+template <int N>
+struct StageRecorder {
+  static constexpr bool kStopAtLast = true;
+  static constexpr int kRows = N + 4;
+  double* col;
+  template <class V>
+  RKMI_HD void first(const V& w0, double mut1) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) col[k * kLdsStride] = w0[k];
+    col[N * kLdsStride] = mut1;
+  }
+  template <class V>
+  RKMI_HD void stage(int j, const V& w, double mu, double nu, double mut, double gt) {
+    double* r = col + (int64_t)(j - 1) * kRows * kLdsStride;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r[k * kLdsStride] = w[k];
+    r[N * kLdsStride] = mu;
+    r[(N + 1) * kLdsStride] = nu;
+    r[(N + 2) * kLdsStride] = mut;
+    r[(N + 3) * kLdsStride] = gt;
+  }
+};
+
+// Rows of a lane's adjoint columns: max_stages stage records, K step starts.
+template <class Prob>
+RKMI_HD int64_t adjoint_rows(int max_stages, int K) {
+  return (int64_t)max_stages * (Prob::N + 4) + (int64_t)K * Prob::N;
+}
+
+// Forward integration of system i with its tape.
+template <class Prob>
+RKMI_HD void taped_system(const typename Prob::Params& prm, int64_t n, int64_t i,
+                          const double* y0, double* y1, const double* g, const Ctl& c,
+                          int32_t* status, int32_t* stats, const TapeView& T, double* slot) {
+  TapeRec<Prob::N> R{T, i, false};
+  Driver<Prob, kMethodRkc, TapeRec<Prob::N>> D;
+  D.rec = &R;
+  const bool go = D.start(prm, c, n, i, y0, g, slot);
+  R.checkpoint(0, D.S.yn);
+  if (go)
+    while (D.attempt(prm, c, slot)) {
+    }
+  D.finish(n, i, y1, status, stats);
+  T.count[i] = R.full ? -1 : (int32_t)D.S.nstep;
+}
+
+// Reverse sweep of system i; returns its status.  lambda = w[:, i] on entry,
+// dL/dy0 and the per-system dL/dtheta on exit (NaN when the tape is
+// incomplete).
+template <class Prob>
+RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int64_t i,
+                               const double* g, const TapeView& T, int max_stages,
+                               const double* w, double* dy0, double* dth, double* slot,
+                               double* col) {
+  constexpr int N = Prob::N, NT = Prob::kNTheta;
+  using V = RegVec<N>;
+  typename Prob::Lane L;
+  Prob::init(L, prm, g, i, n, slot);
+  const int64_t M = T.count[i];
+  V lam;
+  double th[NT];
+#pragma unroll
+  for (int k = 0; k < N; ++k) lam[k] = w[(int64_t)k * n + i];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) th[q] = 0.0;
+  int32_t st = M < 0 ? kSysTape : kSysOk;
+  double* const ys = col + (int64_t)max_stages * StageRecorder<N>::kRows * kLdsStride;
+  for (int64_t seg = M > 0 ? (M - 1) / T.K : -1; st == kSysOk && seg >= 0; --seg) {
+    const int64_t k0 = seg * T.K;
+    const int64_t k1 = (k0 + T.K < M) ? k0 + T.K : M;
+    // step-start states of the segment, from its checkpoint
+    V y;
+#pragma unroll
+    for (int r = 0; r < N; ++r) y[r] = T.ckpt[(seg * N + r) * n + i];
+    for (int64_t k = k0; k < k1; ++k) {
+      double* const yk = ys + (k - k0) * N * kLdsStride;
+#pragma unroll
+      for (int r = 0; r < N; ++r) yk[r * kLdsStride] = y[r];
+      if (k + 1 < k1) {
+        V F, yn;
+        Prob::rhs(L, prm, y, F);
+        rkc_step<Prob>(L, prm, y, F, T.h[k * n + i], T.s[k * n + i], yn, slot);
+        y = yn;
+      }
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const int sk = T.s[k * n + i];
+      const double hk = T.h[k * n + i];
+      if (sk < 2 || sk > max_stages) {
+        st = kSysTape;
+        break;
+      }
+      const double* const yk = ys + (k - k0) * N * kLdsStride;
+#pragma unroll
+      for (int r = 0; r < N; ++r) y[r] = yk[r * kLdsStride];
+      {
+        V F, wlast;
+        Prob::rhs(L, prm, y, F);
+        StageRecorder<N> R{col};
+        rkc_step<Prob, StageRecorder<N>>(L, prm, y, F, hk, sk, wlast, slot, &R);
+      }
+      V cur, m1, m2, A0, f0b, u, jtu, Wv;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        cur[r] = lam[r];
+        m1[r] = 0.0;
+        m2[r] = 0.0;
+        A0[r] = 0.0;
+        f0b[r] = 0.0;
+      }
+      for (int j = sk; j >= 2; --j) {
+        const double* const rj = col + (int64_t)(j - 1) * StageRecorder<N>::kRows * kLdsStride;
+#pragma unroll
+        for (int r = 0; r < N; ++r) Wv[r] = rj[r * kLdsStride];
+        const double mu = rj[N * kLdsStride], nu = rj[(N + 1) * kLdsStride];
+        const double mut = rj[(N + 2) * kLdsStride], gt = rj[(N + 3) * kLdsStride];
+        const double c0 = 1.0 - mu - nu;
+        const double gh = gt * hk, mh = mut * hk;
+        if (j > 2) {
+#pragma unroll
+          for (int r = 0; r < N; ++r) {
+            A0[r] += c0 * cur[r];
+            m1[r] += mu * cur[r];
+            m2[r] += nu * cur[r];
+            f0b[r] += gh * cur[r];
+            u[r] = mh * cur[r];
+          }
+        } else {
+          // w_{j-2} is w_0
+#pragma unroll
+          for (int r = 0; r < N; ++r) {
+            A0[r] += c0 * cur[r];
+            m1[r] += mu * cur[r];
+            A0[r] += nu * cur[r];
+            f0b[r] += gh * cur[r];
+            u[r] = mh * cur[r];
+          }
+        }
+        Prob::vjp(L, prm, Wv, u, jtu, th);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          cur[r] = m1[r] + jtu[r];
+          m1[r] = m2[r];
+          m2[r] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < N; ++r) Wv[r] = col[r * kLdsStride];
+      const double mh1 = col[N * kLdsStride] * hk;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        A0[r] += cur[r];
+        f0b[r] += mh1 * cur[r];
+      }
+      Prob::vjp(L, prm, Wv, f0b, jtu, th);
+#pragma unroll
+      for (int r = 0; r < N; ++r) lam[r] = A0[r] + jtu[r];
+    }
+  }
+  const double nan = crm::from_bits(0x7ff8000000000000ull);
+#pragma unroll
+  for (int k = 0; k < N; ++k) dy0[(int64_t)k * n + i] = st == kSysOk ? lam[k] : nan;
+  if (dth)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) dth[(int64_t)q * n + i] = st == kSysOk ? th[q] : nan;
+  return st;
+}
+
+template <class Prob>
+__global__ __launch_bounds__(kLdsStride) void taped_kernel(typename Prob::Params prm, int64_t n,
+                                                           const double* y0, double* y1,
+                                                           const double* __restrict__ g, Ctl c,
+                                                           int32_t* __restrict__ status,
+                                                           int32_t* __restrict__ stats,
+                                                           TapeView T) {
+  __shared__ double lds[kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride];
+  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
+  if (i >= n) return;
+  taped_system<Prob>(prm, n, i, y0, y1, g, c, status, stats, T, lds + threadIdx.x);
+}
+
+template <class Prob>
+__global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Params prm, int64_t n,
+                                                             const double* __restrict__ g,
+                                                             TapeView T, int max_stages,
+                                                             const double* __restrict__ w,
+                                                             double* __restrict__ dy0,
+                                                             double* __restrict__ dth,
+                                                             int32_t* __restrict__ status,
+                                                             double* cols) {
+  __shared__ double lds[kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride];
+  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
+  if (i >= n) return;
+  double* const col =
+      cols + (int64_t)blockIdx.x * adjoint_rows<Prob>(max_stages, T.K) * kLdsStride + threadIdx.x;
+  const int32_t st =
+      adjoint_system<Prob>(prm, n, i, g, T, max_stages, w, dy0, dth, lds + threadIdx.x, col);
+  if (status) status[i] = st;
+}
+
+// Bytes of adjoint workspace for n systems (one column block per 64 systems).
+template <class Prob>
+int64_t adjoint_workspace_bytes(int64_t n, int max_stages, int K) {
+  const int64_t blocks = (n + kLdsStride - 1) / kLdsStride;
+  return blocks * adjoint_rows<Prob>(max_stages, K) * kLdsStride * (int64_t)sizeof(double);
+}
+
+template <class Prob>
+int launch_taped(const LaunchArgs* a, const TapeArgs* t, void* stream) {
+  static_assert(!Prob::kColumns, "the adjoint keeps the system's vectors in registers");
+  const int64_t blocks = (a->n + kLdsStride - 1) / kLdsStride;
+  if (blocks <= 0) return kLaunchOk;
+  if (blocks > 0x7fffffffLL) return kLaunchInvalid;
+  if (!t->tape || t->K < 1 || t->cap < 0 ||
+      t->tape_bytes < tape_layout(a->n, t->cap, t->K, Prob::N).bytes)
+    return kLaunchWorkspace;
+  const TapeView T = tape_view(*t, a->n, Prob::N);
+  taped_kernel<Prob><<<dim3((unsigned)blocks), dim3(kLdsStride), 0,
+                       static_cast<hipStream_t>(stream)>>>(a->prm, a->n, a->y0, a->y1, a->g,
+                                                           a->ctl, a->status, a->stats, T);
+  return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
+}
+
+template <class Prob>
+int launch_adjoint(const AdjointArgs* a, void* stream) {
+  const int64_t blocks = (a->n + kLdsStride - 1) / kLdsStride;
+  if (blocks <= 0) return kLaunchOk;
+  if (blocks > 0x7fffffffLL) return kLaunchInvalid;
+  if (!a->tape.tape || a->tape.K < 1 || a->tape.cap < 0 ||
+      a->tape.tape_bytes < tape_layout(a->n, a->tape.cap, a->tape.K, Prob::N).bytes)
+    return kLaunchInvalid;
+  if (a->max_stages < 2 || !a->ws ||
+      a->ws_bytes < (size_t)adjoint_workspace_bytes<Prob>(a->n, a->max_stages, a->tape.K))
+    return kLaunchWorkspace;
+  const TapeView T = tape_view(a->tape, a->n, Prob::N);
+  adjoint_kernel<Prob><<<dim3((unsigned)blocks), dim3(kLdsStride), 0,
+                         static_cast<hipStream_t>(stream)>>>(
+      a->prm, a->n, a->g, T, a->max_stages, a->w, a->dy0, a->dth, a->status,
+      static_cast<double*>(a->ws));
+  return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
+}
+
+// Host builds of the same per-system code (test hooks over host arrays).
+template <class Prob>
+int host_taped(const LaunchArgs* a, const TapeArgs* t) {
+  if (!t->tape || t->K < 1 || t->tape_bytes < tape_layout(a->n, t->cap, t->K, Prob::N).bytes)
+    return kLaunchWorkspace;
+  const TapeView T = tape_view(*t, a->n, Prob::N);
+  std::vector<double> slot((size_t)kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride);
+  for (int64_t i = 0; i < a->n; ++i)
+    taped_system<Prob>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T,
+                       slot.data());
+  return kLaunchOk;
+}
+
+template <class Prob>
+int host_adjoint(const AdjointArgs* a) {
+  if (!a->tape.tape || a->tape.K < 1 || a->max_stages < 2 ||
+      a->tape.tape_bytes < tape_layout(a->n, a->tape.cap, a->tape.K, Prob::N).bytes)
+    return kLaunchInvalid;
+  const TapeView T = tape_view(a->tape, a->n, Prob::N);
+  std::vector<double> slot((size_t)kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride);
+  std::vector<double> col((size_t)adjoint_rows<Prob>(a->max_stages, a->tape.K) * kLdsStride);
+  for (int64_t i = 0; i < a->n; ++i) {
+    const int32_t st = adjoint_system<Prob>(a->prm, a->n, i, a->g, T, a->max_stages, a->w,
+                                            a->dy0, a->dth, slot.data(), col.data());
+    if (a->status) a->status[i] = st;
+  }
+  return kLaunchOk;
+}
+
+}  // namespace rkmi

@@ -337,12 +337,30 @@ RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
   w1 = Dm1 / Em1;
 }
 
+// Observer of the stages of an RKC step (the adjoint records them): first()
+// sees w_0 and mut_1, stage(j, ...) sees w_{j-1} with the coefficients of
+// stage j before f(w_{j-1}) is formed.  With kStopAtLast the step ends after
+// stage(s, ...), without forming w_s.
+struct NoSink {
+  static constexpr bool kStopAtLast = false;
+  template <class V>
+  RKMI_HD void first(const V&, double) {}
+  template <class V>
+  RKMI_HD void stage(int, const V&, double, double, double, double) {}
+};
+
+// Observer of accepted RKC steps (the adjoint's forward tape).
+struct NoRec {
+  template <class V>
+  RKMI_HD void accept(double, int, const V&, int64_t) {}
+};
+
 // One RKC step of s stages from (y_n, F_n = f(y_n)) into y (Eqs. E:rkc0 - E:rkcs);
 // the coefficients b_j, mu_j, nu_j, mut_j, gt_j are formed stage by stage.
-template <class Prob>
+template <class Prob, class Sink = NoSink>
 RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params& prm,
                       const Vec<Prob>& yn, const Vec<Prob>& Fn, double h, int s, Vec<Prob>& y,
-                      double* slot) {
+                      double* slot, Sink* sink = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
   double w0, w1;
   rkc_omegas(s, w0, w1);
@@ -356,7 +374,9 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
   double bjm1 = b2, bjm2 = b2;           // b_1 = b_0 = b_2
   double ajm1 = 1.0 - bjm1 * w0;         // a_1 = 1 - b_1 T_1
   Vec<Prob> wjm2 = work_vec<Prob>(slot, kCWm2), f = work_vec<Prob>(slot, kCFs);
-  const double mh1 = (bjm1 * w1) * h;    // mut_1 h
+  const double mut1 = bjm1 * w1;
+  const double mh1 = mut1 * h;           // mut_1 h
+  if (sink) sink->first(yn, mut1);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
     wjm2[i] = yn[i];
@@ -373,6 +393,10 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
     const double gt = -ajm1 * mut;
     const double c0 = 1.0 - mu - nu;
     const double mh = mut * h, gh = gt * h;
+    if (sink) {
+      sink->stage(j, y, mu, nu, mut, gt);
+      if (Sink::kStopAtLast && j == s) return;
+    }
     eval_rhs<Prob>(L, prm, y, f);
 #pragma unroll U
     for (int i = 0; i < N; ++i) {
@@ -531,9 +555,9 @@ RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params
 
 // One attempted step of the RKC driver (Sec. 3.2); returns true while the
 // system still has to step (t < t1 and no failure).
-template <class Prob>
+template <class Prob, class Rec = NoRec>
 RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                         const Ctl& c, RkcState<Prob>& S, double* slot) {
+                         const Ctl& c, RkcState<Prob>& S, double* slot, Rec* rec = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
   const double hmax = c.hmax, hmin = c.hmin_rkc;
   if (S.attempts >= c.max_steps) {
@@ -620,6 +644,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     S.have_prev = true;
     copy<Prob>(S.yn, y);
     copy<Prob>(S.Fn, F1);
+    if (rec) rec->accept(S.h, m, S.yn, S.nstep);
     S.h = S.h * fmax(kP1, fac);
     S.h = fmax(hmin, fmin(hmax, S.h));
     if (!all_finite<Prob>(S.yn)) {
@@ -643,11 +668,11 @@ RKMI_HD void rkc_stats(const RkcState<Prob>& S, int32_t (&st)[kNStats]) {
 // A lane's integration of one system, in four parts: start (load state and
 // parameters, per-system constants, restart state), attempt (one attempted
 // step; false once the system is finished), finish (store).
-template <class Prob, int Method>
+template <class Prob, int Method, class Rec = NoRec>
 struct Driver;
 
-template <class Prob>
-struct Driver<Prob, kMethodRkck> {
+template <class Prob, class Rec>
+struct Driver<Prob, kMethodRkck, Rec> {
   static constexpr int N = Prob::N, U = kUnroll<Prob>;
   typename Prob::Lane L;
   RkckState<Prob> S;
@@ -675,11 +700,12 @@ struct Driver<Prob, kMethodRkck> {
   }
 };
 
-template <class Prob>
-struct Driver<Prob, kMethodRkc> {
+template <class Prob, class Rec>
+struct Driver<Prob, kMethodRkc, Rec> {
   static constexpr int N = Prob::N, U = kUnroll<Prob>;
   typename Prob::Lane L;
   RkcState<Prob> S;
+  Rec* rec = nullptr;
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
                      const double* y0, const double* g, double* slot) {
     Prob::init(L, prm, g, i, n, slot);
@@ -690,7 +716,7 @@ struct Driver<Prob, kMethodRkc> {
     return S.t < c.t1;
   }
   RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
-    return rkc_attempt<Prob>(L, prm, c, S, slot);
+    return rkc_attempt<Prob, Rec>(L, prm, c, S, slot, rec);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
 #pragma unroll U
@@ -753,28 +779,21 @@ __global__ __launch_bounds__(kLdsStride) void plain_kernel(typename Prob::Params
                                  lane_slot<Prob, Method>(lds, cols));
 }
 
-// Persistent kernel: a grid sized to the machine; finished lanes take the next
-// systems from a device-wide queue while the other lanes of their wave carry
-// on, so lanes are not left idle behind the slowest system of a fixed group.
-// A wave refills once at least c.refill of its lanes are idle (or all its
-// live lanes are): the systems started together form a cohort that runs its
-// set-up and its periodic spectral-radius estimates in step, instead of each
-// new lane running them alone.  The lanes taking work share one atomic add
-// (wave-aggregated).  The queue head is queue[0] and must be zero at launch.
-// A lane retires once the queue is exhausted; the wave exits when all its
-// lanes have retired, so every wave terminates.
+// Persistent loop of one wave over the systems of one queue: finished lanes
+// take the next systems from a device-wide queue while the other lanes of
+// their wave carry on, so lanes are not left idle behind the slowest system
+// of a fixed group.  A wave refills once at least c.refill of its lanes are
+// idle (or all its live lanes are): the systems started together form a
+// cohort that runs its set-up and its periodic spectral-radius estimates in
+// step, instead of each new lane running them alone.  The lanes taking work
+// share one atomic add (wave-aggregated).  A lane retires once the queue is
+// exhausted; the loop ends when all the wave's lanes have retired, so every
+// wave leaves it.  Called by all 64 lanes of the wave.
 template <class Prob, int Method>
-__global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::Params prm,
-                                                                int64_t n, const double* y0,
-                                                                double* y1,
-                                                                const double* __restrict__ g,
-                                                                Ctl c, int32_t* __restrict__ status,
-                                                                int32_t* __restrict__ stats,
-                                                                unsigned long long* queue,
-                                                                double* cols) {
-  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
+__device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, const double* y0,
+                                double* y1, const double* g, const Ctl& c, int32_t* status,
+                                int32_t* stats, unsigned long long* queue, double* slot) {
   const int lane = threadIdx.x;
-  double* slot = lane_slot<Prob, Method>(lds, cols);
   Driver<Prob, Method> D;
   int64_t i = -1;
   bool active = false, retired = false;
@@ -808,6 +827,22 @@ __global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::P
       active = false;
     }
   }
+}
+
+// Persistent kernel: a grid sized to the machine running persistent_loop over
+// the queue whose head, queue[0], must be zero at launch.
+template <class Prob, int Method>
+__global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::Params prm,
+                                                                int64_t n, const double* y0,
+                                                                double* y1,
+                                                                const double* __restrict__ g,
+                                                                Ctl c, int32_t* __restrict__ status,
+                                                                int32_t* __restrict__ stats,
+                                                                unsigned long long* queue,
+                                                                double* cols) {
+  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
+  persistent_loop<Prob, Method>(prm, n, y0, y1, g, c, status, stats, queue,
+                                lane_slot<Prob, Method>(lds, cols));
 }
 
 }  // namespace rkmi

@@ -1,6 +1,6 @@
 // rk_vdp.hip -- van der Pol oscillators, y1' = y2, y2' = mu (1 - y1^2) y2 - y1,
 // one parameter g = (mu) per system: the nonstiff RKCK workload.
-#include "rk_launch.hpp"
+#include "rk_adjoint.hpp"
 
 namespace rkmi {
 
@@ -21,6 +21,15 @@ struct VdpProblem {
     f[0] = y[1];
     f[1] = L.mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
   }
+  // vector-Jacobian products, theta = mu: jtu = J(y)^T u, th += (df/dmu)^T u
+  static constexpr int kNTheta = 1;
+  template <class VI, class VU, class VO>
+  RKMI_HD static void vjp(const Lane& L, const Params&, const VI& y, const VU& u, VO& jtu,
+                          double (&th)[1]) {
+    jtu[0] = u[1] * (-2.0 * L.mu * y[0] * y[1] - 1.0);
+    jtu[1] = u[0] + u[1] * L.mu * (1.0 - y[0] * y[0]);
+    th[0] += u[1] * (1.0 - y[0] * y[0]) * y[1];
+  }
 };
 
 }  // namespace rkmi
@@ -35,4 +44,20 @@ extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a) {
 
 extern "C" int64_t rkmi_vdp_workspace(int method, int schedule, int64_t n) {
   return rkmi::workspace<rkmi::VdpProblem>(method, schedule, n);
+}
+
+extern "C" int rkmi_vdp_taped(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t, void* s) {
+  return rkmi::launch_taped<rkmi::VdpProblem>(a, t, s);
+}
+
+extern "C" int rkmi_vdp_taped_host(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t) {
+  return rkmi::host_taped<rkmi::VdpProblem>(a, t);
+}
+
+extern "C" int rkmi_vdp_adjoint(const rkmi::AdjointArgs* a, void* s) {
+  return rkmi::launch_adjoint<rkmi::VdpProblem>(a, s);
+}
+
+extern "C" int rkmi_vdp_adjoint_host(const rkmi::AdjointArgs* a) {
+  return rkmi::host_adjoint<rkmi::VdpProblem>(a);
 }

@@ -17,6 +17,11 @@ Per-unit counts (N unknowns, NR reactions, S = reactant+product slots in use):
                    error estimate and weights 9N, controller 10)
   power method     6N per call + 6N per iteration beyond its right-hand sides
   RKC first step   7N
+  adjoint VJP      van der Pol: 15;  mass action: 21NR + 8N (J^T u and the
+                   ln A contributions)
+  adjoint step     s VJPs + (s - 1)(10N + 4) + 4N + 1 per accepted step of s
+                   stages (the transposed recursion), beyond the forward
+                   integration; recomputation from checkpoints is not counted
 """
 from __future__ import annotations
 
@@ -56,3 +61,15 @@ def per_system(method: str, stats: np.ndarray, n_eq: int, net=None) -> np.ndarra
 
 def total(method: str, stats, n_eq: int, net=None) -> float:
     return float(per_system(method, stats, n_eq, net).sum())
+
+
+def vjp_flops(net=None) -> int:
+    return 15 if net is None else 21 * net.n_rx + 8 * net.n_sp
+
+
+def adjoint_reverse(n_eq: int, net, n_steps, stage_sum) -> float:
+    """Flops of the reverse sweep: n_steps accepted steps whose stage counts sum
+    to stage_sum (totals over all systems)."""
+    V = vjp_flops(net)
+    N = n_eq
+    return float(stage_sum * V + (stage_sum - n_steps) * (10 * N + 4) + n_steps * (4 * N + 1))

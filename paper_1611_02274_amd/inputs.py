@@ -252,6 +252,17 @@ def ragged_inputs(n_total: int = 1_000_000, seed: int = 4004, T_range=(800.0, 30
     return slot_net, per_net
 
 
+def slot_map_codes(slot_net: np.ndarray) -> np.ndarray:
+    """Slot map of the interleaved batch form: code (network << 28 | index of the
+    system within its network's block), systems numbered in slot order."""
+    slot_net = np.asarray(slot_net, dtype=np.int32)
+    local = np.zeros(slot_net.size, dtype=np.int32)
+    for k in np.unique(slot_net):
+        sel = slot_net == k
+        local[sel] = np.arange(int(sel.sum()), dtype=np.int32)
+    return (slot_net.astype(np.int32) << 28) | local
+
+
 def linear_problem_matrix(eigs, seed: int = 0) -> np.ndarray:
     """A dense matrix with the given real eigenvalues and a random orthogonal
     eigenbasis (symmetric, so the spectral radius is max |eig|)."""

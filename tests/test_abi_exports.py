@@ -16,7 +16,7 @@ def _declared():
 
 def test_header_declares_entry_points():
     names = _declared()
-    for want in ("rk_integrate_rkck", "rk_integrate_rkc", "rk_problem_create_vdp",
+    for want in ("rk_integrate_rkck", "rk_integrate_rkc", "rk_adjoint_rkc", "rk_problem_create_vdp",
                  "rk_problem_create_mass_action", "rk_last_error"):
         assert want in names
 
@@ -39,3 +39,22 @@ def test_host_only_calls():
     L = rk._lib.lib()
     assert L.rk_problem_create_vdp(None) == rk._lib.RK_EINVAL
     assert b"NULL" in L.rk_last_error()
+
+
+def test_batch_create_host_only():
+    """A batch handle is found for the compiled set of networks in any order and
+    refused for a set without a compiled batch kernel (no device touched)."""
+    import ctypes as C
+
+    import paper_1611_02274_amd as rk
+    nets = [rk.inputs.standard_network(k) for k in (53, 9, 32, 13)]
+    b = rk.Batch([rk.Problem.network(n) for n in nets])
+    assert b._h
+    L = rk._lib.lib()
+    two = [rk.Problem.network(n) for n in nets[:2]]
+    arr = (C.c_void_p * 2)(*[p.handle.value for p in two])
+    h = C.c_void_p()
+    assert L.rk_batch_create(arr, 2, C.byref(h)) == rk._lib.RK_EUNSUPPORTED
+    vdp = rk.Problem.vdp()
+    arr1 = (C.c_void_p * 1)(vdp.handle.value)
+    assert L.rk_batch_create(arr1, 1, C.byref(h)) == rk._lib.RK_EINVAL
