@@ -127,10 +127,16 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
 
 /* Schedules.  Plain: one lane per system, system i on global lane i (the
  * paper's intDriver, Sec. 3).  Persistent: a machine-sized grid whose lanes take
- * the next system from a device-side queue as soon as theirs is finished. */
+ * the next system from a device-side queue as soon as theirs is finished.
+ * Group: for networks of more than 16 species, 16 lanes of a wave share one
+ * system (its vectors and rate constants spread over their registers, its
+ * concentrations and rates exchanged through LDS), groups taking systems
+ * from the queue; other problems run their default.  Auto: group where
+ * available, else persistent (plain without a workspace). */
 #define RK_SCHED_AUTO 0
 #define RK_SCHED_PLAIN 1
 #define RK_SCHED_PERSISTENT 2
+#define RK_SCHED_GROUP 3
 
 #define RK_METHOD_RKCK 0
 #define RK_METHOD_RKC 1

@@ -180,7 +180,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if (opt) {
     for (int k = 0; k < 6; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
-    if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedPersistent)
+    if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedGroup)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
   }
   if (n == 0) return RK_OK;
@@ -347,7 +347,7 @@ size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_
   g_err.clear();
   if (!p || n_sys <= 0 || (method != RK_METHOD_RKCK && method != RK_METHOD_RKC)) return 0;
   const int schedule = opt ? opt->schedule : rkmi::kSchedAuto;
-  if (schedule < rkmi::kSchedAuto || schedule > rkmi::kSchedPersistent) return 0;
+  if (schedule < rkmi::kSchedAuto || schedule > rkmi::kSchedGroup) return 0;
   const int64_t b = p->workspace(method == RK_METHOD_RKCK ? rkmi::kMethodRkck : rkmi::kMethodRkc,
                                  schedule, n_sys);
   if (b < 0) {

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <vector>
 
+#include "rk_group.hpp"
 #include "rk_launch.hpp"
 
 namespace rkmi {
@@ -47,21 +48,50 @@ struct BatchParams {
   int64_t col_block;
 };
 
+// LDS doubles of a workgroup running Prob's persistent loop (one lane per
+// system, or the group variant).
+template <class Prob>
+constexpr int persistent_lds_doubles() {
+  if constexpr (Prob::kGroupLanes > 1)
+    return group_lds_doubles<Prob>();
+  else
+    return kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride;
+}
+
 template <class... P>
 constexpr int batch_lds_doubles() {
-  int m = 1;
-  ((m = kernel_lds_doubles<P, kMethodRkc>() > m ? kernel_lds_doubles<P, kMethodRkc>() : m), ...);
+  int m = kLdsStride;
+  ((m = persistent_lds_doubles<typename FastVariant<P>::type>() > m
+            ? persistent_lds_doubles<typename FastVariant<P>::type>()
+            : m),
+   ...);
+  ((m = kernel_lds_doubles<P, kMethodRkc>() * kLdsStride > m
+            ? kernel_lds_doubles<P, kMethodRkc>() * kLdsStride
+            : m),
+   ...);
   return m;
 }
 
-// Column doubles one workgroup needs (the largest column-held network's block).
-template <class... P>
+template <class Prob>
+constexpr int64_t col_block_of() {
+  return (Prob::kGroupLanes == 1 && Prob::kColumns)
+             ? (int64_t)slot_doubles<Prob, kMethodRkc>() * kLdsStride
+             : 0;
+}
+
+// Column doubles one workgroup needs: the largest column-held network's block
+// among the kernels' variants (Fast = the persistent kernel's, else the plain
+// forms').
+template <bool Fast, class... P>
 constexpr int64_t batch_col_block() {
   int64_t m = 0;
-  ((m = (P::kColumns && (int64_t)slot_doubles<P, kMethodRkc>() * kLdsStride > m)
-            ? (int64_t)slot_doubles<P, kMethodRkc>() * kLdsStride
-            : m),
-   ...);
+  if constexpr (Fast)
+    ((m = col_block_of<typename FastVariant<P>::type>() > m
+              ? col_block_of<typename FastVariant<P>::type>()
+              : m),
+     ...);
+  else
+    ((m = col_block_of<P>() > m ? col_block_of<P>() : m), ...);
   return m;
 }
 
@@ -69,19 +99,25 @@ template <class Prob>
 __device__ void batch_run_net(const BatchNet& d, Ctl c, int refill, unsigned long long* queue,
                               double* lds, double* colbase) {
   c.refill = refill;
-  double* slot = Prob::kColumns ? colbase + threadIdx.x : lds + threadIdx.x;
-  persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats, queue, slot);
+  if constexpr (Prob::kGroupLanes > 1) {
+    group_persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats,
+                                            queue, lds);
+  } else {
+    double* slot = Prob::kColumns ? colbase + threadIdx.x : lds + threadIdx.x;
+    persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats, queue,
+                                      slot);
+  }
 }
 
 template <class... P>
 __global__ __launch_bounds__(kLdsStride) void ragged_kernel(BatchParams bp, Ctl c) {
-  __shared__ double lds[batch_lds_doubles<P...>() * kLdsStride];
+  __shared__ double lds[batch_lds_doubles<P...>()];
   double* const colbase = bp.cols ? bp.cols + (int64_t)blockIdx.x * bp.col_block : nullptr;
   for (int r = 0; r < bp.n_net; ++r) {
     const int k = bp.order[r];
     int idx = 0;
-    ((idx++ == k ? batch_run_net<P>(bp.net[k], c, bp.refill[k], bp.queues + k * kQueueStride,
-                                    lds, colbase)
+    ((idx++ == k ? batch_run_net<typename FastVariant<P>::type>(
+                       bp.net[k], c, bp.refill[k], bp.queues + k * kQueueStride, lds, colbase)
                  : void()),
      ...);
   }
@@ -104,7 +140,7 @@ template <class... P>
 __global__ __launch_bounds__(kLdsStride) void interleaved_kernel(BatchParams bp, Ctl c,
                                                                  const int32_t* __restrict__ map,
                                                                  int64_t n_total) {
-  __shared__ double lds[batch_lds_doubles<P...>() * kLdsStride];
+  __shared__ double lds[batch_lds_doubles<P...>()];
   const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n_total) return;
   const int32_t code = map[i];
@@ -182,19 +218,21 @@ BatchParams batch_params(const BatchArgs* a) {
   bp.n_net = (int32_t)sizeof...(P);
   unsigned char* ws = static_cast<unsigned char*>(a->ws);
   bp.queues = reinterpret_cast<unsigned long long*>(ws);
-  bp.col_block = batch_col_block<P...>();
+  bp.col_block = a->mode == kBatchPersistent ? batch_col_block<true, P...>()
+                                             : batch_col_block<false, P...>();
   bp.cols = bp.col_block ? reinterpret_cast<double*>(ws + kBatchQueueBytes) : nullptr;
   return bp;
 }
 
 template <class... P>
 int64_t batch_workspace(const BatchArgs* a) {
-  constexpr int64_t cb = batch_col_block<P...>() * (int64_t)sizeof(double);
   if (a->mode == kBatchPersistent) {
+    constexpr int64_t cb = batch_col_block<true, P...>() * (int64_t)sizeof(double);
     int64_t grid = 0;
     if (ragged_grid<P...>(a->waves_per_cu, &grid) != kLaunchOk) return -1;
     return (int64_t)kBatchQueueBytes + grid * cb;
   }
+  constexpr int64_t cb = batch_col_block<false, P...>() * (int64_t)sizeof(double);
   if (a->mode == kBatchInterleaved)
     return (int64_t)kBatchQueueBytes + (a->n_total + kLdsStride - 1) / kLdsStride * cb;
   int64_t m = 0, k = 0;

@@ -11,7 +11,7 @@
 
 namespace rkmi {
 
-enum : int { kSchedAuto = 0, kSchedPlain = 1, kSchedPersistent = 2 };
+enum : int { kSchedAuto = 0, kSchedPlain = 1, kSchedPersistent = 2, kSchedGroup = 3 };
 
 // Launch error codes (mapped to RK_* by the ABI layer).
 enum : int { kLaunchOk = 0, kLaunchInvalid = -1, kLaunchHip = -3, kLaunchWorkspace = -5 };
@@ -74,9 +74,11 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
   double* const cols = ws ? reinterpret_cast<double*>(ws + kQueueBytes) : nullptr;
   // persistent when asked, or by default when the workspace holds the queue and
   // at least one workgroup's columns
+  // (the group schedule means the default one for problems without a group variant)
   const bool persistent =
       a->schedule == kSchedPersistent ||
-      (a->schedule == kSchedAuto && ws_bytes >= kQueueBytes + col_bytes);
+      ((a->schedule == kSchedAuto || a->schedule == kSchedGroup) &&
+       ws_bytes >= kQueueBytes + col_bytes);
   if (!persistent) {
     if (col_bytes && ws_bytes < kQueueBytes + (size_t)blocks * col_bytes) return kLaunchWorkspace;
     plain_kernel<Prob, Method><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(

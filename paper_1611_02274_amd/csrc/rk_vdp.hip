@@ -7,6 +7,7 @@ namespace rkmi {
 struct VdpProblem {
   static constexpr int N = 2;
   static constexpr bool kColumns = false;
+  static constexpr int kGroupLanes = 1;
   static constexpr int kLaneDoubles = 0;
   using Params = const double*;
   struct Lane {
