@@ -312,10 +312,8 @@ struct GRkc {
     have_prev = false;
   }
 
-  // Nonlinear power method (Appendix), as spec_rad.  Outlined: it runs every
-  // sr_period accepted steps and after rejections, and one copy instead of two
-  // keeps the attempt's register demand down.
-  __device__ __noinline__ double spec_rad(const Grp<GP>& x, double hmax, int itmax, int& iters) {
+  // Nonlinear power method (Appendix), as spec_rad.
+  __device__ double spec_rad(const Grp<GP>& x, double hmax, int itmax, int& iters) {
     double Fv[S], t2[S];
     const double sq = sqrt(kUround);
     const double small = 1.0 / hmax;
