@@ -7,7 +7,7 @@
 // right-hand side exchanges concentrations and rates of progress through the
 // group's LDS area:
 //   1. owners write C_k = (rho Y_k) / W_k; lane 0 forms [M] = sum_k C_k;
-//   2. owners of reaction j write q_j = k_f prod_R C - k_r prod_P C;
+//   2. owners of reaction j write q_j = k_f prod_R C - k_r prod_P C and -q_j;
 //   3. owners of species k sum their signed q_j in reaction order, then
 //      f_k = (W_k omega_k) / rho,
 // which is the per-system evaluation order, so results equal the one-lane
@@ -131,7 +131,9 @@ __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const do
       opaque(code);
       const double ca = C[code & 0xffu], cb = C[(code >> 8) & 0xffu];
       const double cc = C[(code >> 16) & 0xffu], cd = C[code >> 24];
-      Q[j] = (L.kf[m] * ca) * cb - (L.kr[m] * cc) * cd;
+      const double q = (L.kf[m] * ca) * cb - (L.kr[m] * cc) * cd;
+      Q[j] = q;
+      Q[NR + 1 + j] = -q;
     }
     // bound how far the scheduler moves loads ahead (register pressure)
     if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
@@ -142,15 +144,14 @@ __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const do
     double om = 0.0;
 #pragma unroll
     for (int t = GP::kTermOff[m]; t < GP::kTermOff[m + 1]; ++t) {
-      // term t: kTermBits-bit code (rate index << 1 | negative), packed
-      // kTermsPerWord to a register
+      // term t: kTermBits-bit index into the signed rates, packed
+      // kTermsPerWord to a register; om - q is formed as om + (-q)
       uint32_t word = L.tc[t / GP::kTermsPerWord];
       if (t % GP::kTermsPerWord == 0) opaque(word);
       const uint32_t code = (word >>
                              ((t % GP::kTermsPerWord) * GP::kTermBits)) &
                             ((1u << GP::kTermBits) - 1u);
-      const double q = Q[code >> 1];
-      om = om + ((code & 1u) ? -q : q);
+      om = om + Q[code];
       if (t % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
     f[m] = owns<GP>(x, m) ? (L.W[m] * om) * L.irho : 0.0;
