@@ -255,7 +255,8 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
 }
 
 template <class Prob>
-__global__ __launch_bounds__(kLdsStride) void taped_kernel(typename Prob::Params prm, int64_t n,
+__global__ __launch_bounds__(kLdsStride)
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void taped_kernel(typename Prob::Params prm, int64_t n,
                                                            const double* y0, double* y1,
                                                            const double* __restrict__ g, Ctl c,
                                                            int32_t* __restrict__ status,

@@ -63,6 +63,43 @@ constexpr int kLdsStride = 64;
 enum : int32_t { kSysOk = 0, kSysNonFinite = 1, kSysHmin = 2, kSysMaxSteps = 3 };
 enum : int { kStAccept = 0, kStReject, kStRhs, kStSrCalls, kStPowIters, kStMaxStages, kNStats };
 
+// Read-only, wave-uniform data (the network constants of a launch).  On the
+// device it is read through the constant address space, so the compiler can
+// use scalar loads into scalar registers instead of holding the values in
+// vector registers; the host build reads it plainly.
+RKMI_HD double ld_uniform(const double* p, int k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(4))) double*)p)[k];
+#else
+  return p[k];
+#endif
+}
+
+// Zero, as a value the optimizer cannot see through: memory read at an offset
+// that includes it stays where the source reads it (a loop-invariant read is
+// not hoisted out of the integration loop into live registers).
+RKMI_HD int opaque_zero() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return z;
+#else
+  return 0;
+#endif
+}
+
+// Waves per SIMD the integration kernels of a problem are compiled for: a
+// problem may ask for more than the register allocator would choose by itself
+// (Prob::kWavesPerEu), trading a few spilled bytes for latency hiding.
+template <class P, class = void>
+struct WavesPerEu {
+  static constexpr int value = 1;
+};
+template <class P>
+struct WavesPerEu<P, std::void_t<decltype(P::kWavesPerEu)>> {
+  static constexpr int value = P::kWavesPerEu;
+};
+
 // A vector of N unknowns held in registers.
 template <int N>
 struct RegVec {
@@ -765,7 +802,8 @@ constexpr int kernel_lds_doubles() {
 // Plain kernel: one lane per system, system i = global thread index (the
 // paper's intDriver, Sec. 3).
 template <class Prob, int Method>
-__global__ __launch_bounds__(kLdsStride) void plain_kernel(typename Prob::Params prm, int64_t n,
+__global__ __launch_bounds__(kLdsStride)
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void plain_kernel(typename Prob::Params prm, int64_t n,
                                                            const double* y0,  // may alias y1
                                                            double* y1,
                                                            const double* __restrict__ g, Ctl c,
@@ -832,7 +870,8 @@ __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, con
 // Persistent kernel: a grid sized to the machine running persistent_loop over
 // the queue whose head, queue[0], must be zero at launch.
 template <class Prob, int Method>
-__global__ __launch_bounds__(kLdsStride) void persistent_kernel(typename Prob::Params prm,
+__global__ __launch_bounds__(kLdsStride)
+__attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void persistent_kernel(typename Prob::Params prm,
                                                                 int64_t n, const double* y0,
                                                                 double* y1,
                                                                 const double* __restrict__ g,
