@@ -284,7 +284,12 @@ def main():
                     help="ragged workload: plain forms not to time (interleaved,per_network)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "plain", "persistent"])
+    ap.add_argument("--schedule", default="default",
+                    choices=["default", "auto", "plain", "persistent", "group"],
+                    help="default: the workload's own launch (schedule and cost order)")
+    ap.add_argument("--cost-order", type=int, default=-1,
+                    help="1: hand systems out in decreasing pilot cost; 0: queue order; "
+                         "-1: the workload's own choice")
     ap.add_argument("--refill", type=int, default=0,
                     help="persistent schedule: idle lanes that trigger a refill (0: default)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,11 +339,26 @@ def main():
     status = torch.empty(w.n, dtype=torch.int32, device=dev)
     stats = torch.empty((rk.RK_NSTATS, w.n), dtype=torch.int32, device=dev)
     fn = rk.integrate_rkck if w.method == "rkck" else rk.integrate_rkc
-    sched = {"auto": 0, "plain": 1, "persistent": 2}[args.schedule]
+    launch = dict(w.launch)
+    if args.schedule != "default":
+        launch["schedule"] = {"auto": 0, "plain": 1, "persistent": 2, "group": 3}[args.schedule]
+    if args.cost_order >= 0:
+        launch["cost_order"] = args.cost_order
+    if args.refill:
+        launch["refill"] = args.refill
+    sched_name = {0: "automatic (group for more than 16 species, else persistent)",
+                  1: "plain (one system per lane)",
+                  2: "persistent (lanes refilled from a device queue)",
+                  3: "group (several lanes per system, groups refilled from a device queue)"
+                  }[launch.get("schedule", 0)]
+    if launch.get("cost_order"):
+        sched_name += ("; cost order (a pilot at 1e4 x looser tolerances counts each system's "
+                       "steps, systems handed out in decreasing count; pilot and sort inside "
+                       "the timed step)")
 
     def step():
         fn(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, out=out, status=status, stats=stats,
-           schedule=sched, refill=args.refill)
+           **launch)
 
     for k in range(args.warmup):
         step()
@@ -380,8 +400,7 @@ def main():
         "config": {
             "workload": w.name, "method": w.method, "problem": w.problem, "n_systems": w.n,
             "t0": w.t0, "t1": w.t1, "rtol": w.rtol, "atol": w.atol,
-            "schedule": "persistent (lanes refilled from a device queue)"
-                        if args.schedule != "plain" else "plain (one system per lane)",
+            "schedule": sched_name, "launch": launch,
             "systems_ok": int((status_h == 0).sum()),
             "mean_accepted_steps": float(st_h[0].mean()),
             "mean_rhs_evals": float(st_h[2].mean()),
@@ -391,6 +410,8 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
             "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
             "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops,
+            "kernel_ms_covers": ("pilot, sort and integration kernels of one call"
+                                 if launch.get("cost_order") else "the integration kernel"),
         },
     }
     if not args.no_cpu_baseline:

@@ -98,7 +98,11 @@ typedef struct {
                            enough, else plain), 1 plain, 2 persistent (needs workspace) */
   int32_t refill;       /* persistent schedule: a wave takes new systems once at least this
                            many of its 64 lanes are idle (1..64; <= 0: tuned default) */
-  int32_t reserved[6];  /* set to 0 */
+  int32_t cost_order;   /* nonzero: hand systems to lanes in decreasing order of their cost,
+                           estimated by a pilot integration at loosened tolerances (see
+                           RK_SCHED_* below); results are unchanged.  Not for taped
+                           integrations or batches (RK_EUNSUPPORTED). */
+  int32_t reserved[5];  /* set to 0 */
 } rk_options;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -132,7 +136,17 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
  * system (its vectors and rate constants spread over their registers, its
  * concentrations and rates exchanged through LDS), groups taking systems
  * from the queue; other problems run their default.  Auto: group where
- * available, else persistent (plain without a workspace). */
+ * available, else persistent (plain without a workspace).
+ *
+ * Cost order (rk_options.cost_order, with any schedule): the lanes of a wave
+ * run in lockstep, so a wave lasts as long as its most expensive system.  The
+ * call first integrates every system at rtol and atol multiplied by 10^4
+ * (rtol at most 1e-3, never below the call's own), keeping only each system's
+ * count of attempted steps, sorts the systems by that count on the
+ * device, and then integrates them at the requested tolerances handed out in
+ * decreasing order of it.  Each system's result is bit-for-bit the same as
+ * without the order.  The workspace grows by 24 + 4 bytes per system plus
+ * 33 KiB. */
 #define RK_SCHED_AUTO 0
 #define RK_SCHED_PLAIN 1
 #define RK_SCHED_PERSISTENT 2
@@ -149,8 +163,8 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
  * their rate constants in the workspace: one block per 64 systems for the
  * plain schedule, one per resident workgroup for the persistent one (a smaller
  * workspace, down to one block, runs a smaller persistent grid).  RK_SCHED_AUTO
- * sizes for the persistent schedule.  Returns 0 on a NULL handle or bad
- * method.  The caller allocates it; it must not be shared by calls that may
+ * sizes for the persistent schedule.  With cost_order the order's buffers
+ * follow (256-byte aligned).  Returns 0 on a NULL handle or bad method.  The caller allocates it; it must not be shared by calls that may
  * run concurrently. */
 size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_options *opt);
 

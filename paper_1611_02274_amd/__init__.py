@@ -65,12 +65,13 @@ class Problem:
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h is not None and _lib._lib is not None:
+        if h is not None and _lib is not None and _lib._lib is not None:
             _lib._lib.rk_problem_destroy(h)
 
 
-def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refill=None):
-    if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill)):
+def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refill=None,
+             cost_order=None):
+    if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill, cost_order)):
         return None
     o = _lib.Options()
     o.max_steps = int(max_steps or 0)
@@ -78,6 +79,7 @@ def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refil
     o.sr_itmax = int(sr_itmax or 0)
     o.schedule = int(schedule or 0)
     o.refill = int(refill or 0)
+    o.cost_order = int(bool(cost_order))
     return o
 
 
@@ -325,7 +327,7 @@ class Batch:
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h is not None and _lib._lib is not None:
+        if h is not None and _lib is not None and _lib._lib is not None:
             _lib._lib.rk_batch_destroy(h)
 
     @classmethod

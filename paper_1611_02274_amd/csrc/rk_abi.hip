@@ -15,6 +15,7 @@
 #include "../../include/rkmi.h"
 #include "rk_adjoint.hpp"
 #include "rk_batch.hpp"
+#include "rk_order.hpp"
 
 extern "C" int rkmi_vdp_launch(const rkmi::LaunchArgs* a, void* s);
 extern "C" int rkmi_vdp_host(const rkmi::LaunchArgs* a);
@@ -159,6 +160,8 @@ void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, dou
   a.stats = stats;
   a.ws = ws;
   a.ws_bytes = ws_bytes;
+  a.order = nullptr;
+  a.pilot = 0;
 }
 
 int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1, const double* g,
@@ -178,10 +181,12 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(RK_EINVAL, "rtol must be positive");
   if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(RK_EINVAL, "atol must be >= 0");
   if (opt) {
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 5; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedGroup)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
+    if (opt->cost_order && tape)
+      return fail(RK_EUNSUPPORTED, "cost_order is not available for a taped integration");
   }
   if (n == 0) return RK_OK;
   int rc;
@@ -211,7 +216,13 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
   if ((rc = problem_device_data(p, &a.prm))) return rc;
-  rc = tape ? p->taped(&a, tape, stream) : p->launch(&a, stream);
+  if (opt && opt->cost_order) {
+    const int64_t base = p->workspace(method, a.schedule, n);
+    if (base < 0) return fail(RK_EHIP, "could not query the current device");
+    rc = rkmi::launch_cost_ordered(&a, (size_t)base, p->launch, stream);
+  } else {
+    rc = tape ? p->taped(&a, tape, stream) : p->launch(&a, stream);
+  }
   if (rc == rkmi::kLaunchWorkspace)
     return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (rk_workspace_bytes gives "
                 "the size this call needs)", ws ? ws_bytes : (size_t)0);
@@ -354,6 +365,7 @@ size_t rk_workspace_bytes(rk_problem p, int32_t method, int64_t n_sys, const rk_
     fail(RK_EHIP, "could not query the current device");
     return 0;
   }
+  if (opt && opt->cost_order) return rkmi::order_layout((size_t)b, n_sys).bytes;
   return (size_t)b;
 }
 
@@ -611,9 +623,12 @@ int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
   g_err.clear();
   if (!b) return fail(RK_EINVAL, "batch handle is NULL");
   if (!n_sys || !y || !g) return fail(RK_EINVAL, "n_sys, y and g are required");
-  if (opt)
-    for (int k = 0; k < 6; ++k)
+  if (opt) {
+    for (int k = 0; k < 5; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
+    if (opt->cost_order)
+      return fail(RK_EUNSUPPORTED, "cost_order is not available for a batch");
+  }
   rkmi::BatchArgs a;
   int rc = batch_args(b, n_sys, y, g, status, stats, slot_map, n_total, t0, dt, n_substeps, rtol,
                       atol, opt, sched, ws, ws_bytes, true, a);

@@ -101,11 +101,11 @@ __device__ void batch_run_net(const BatchNet& d, Ctl c, int refill, unsigned lon
   c.refill = refill;
   if constexpr (Prob::kGroupLanes > 1) {
     group_persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats,
-                                            queue, lds);
+                                            queue, lds, nullptr);
   } else {
     double* slot = Prob::kColumns ? colbase + threadIdx.x : lds + threadIdx.x;
     persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats, queue,
-                                      slot);
+                                      slot, nullptr);
   }
 }
 
@@ -266,7 +266,7 @@ int batch_enqueue(const BatchArgs* a, hipStream_t s) {
         la.stats = a->net[k].stats;
         la.ws = a->ws;
         la.ws_bytes = a->ws_bytes;
-        if (rc == kLaunchOk && la.n > 0) rc = launch_method<Prob, kMethodRkc>(&la, s);
+        if (rc == kLaunchOk && la.n > 0) rc = launch_method<Prob, kMethodRkc, false>(&la, s);
         ++k;
       };
       (one(P{}), ...);

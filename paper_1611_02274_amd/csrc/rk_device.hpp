@@ -704,7 +704,8 @@ RKMI_HD void rkc_stats(const RkcState<Prob>& S, int32_t (&st)[kNStats]) {
 
 // A lane's integration of one system, in four parts: start (load state and
 // parameters, per-system constants, restart state), attempt (one attempted
-// step; false once the system is finished), finish (store).
+// step; false once the system is finished), finish (store; a null y1 stores
+// only status and statistics).
 template <class Prob, int Method, class Rec = NoRec>
 struct Driver;
 
@@ -726,8 +727,9 @@ struct Driver<Prob, kMethodRkck, Rec> {
     return rkck_attempt<Prob>(L, prm, c, S, slot);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+    if (y1)
 #pragma unroll U
-    for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.y[k];
+      for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.y[k];
     int32_t st[kNStats];
     rkck_stats(S, st);
     if (status) status[i] = S.status;
@@ -756,8 +758,9 @@ struct Driver<Prob, kMethodRkc, Rec> {
     return rkc_attempt<Prob, Rec>(L, prm, c, S, slot, rec);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+    if (y1)
 #pragma unroll U
-    for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.yn[k];
+      for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.yn[k];
     int32_t st[kNStats];
     rkc_stats(S, st);
     if (status) status[i] = S.status;
@@ -800,8 +803,8 @@ constexpr int kernel_lds_doubles() {
 }
 
 // Plain kernel: one lane per system, system i = global thread index (the
-// paper's intDriver, Sec. 3).
-template <class Prob, int Method>
+// paper's intDriver, Sec. 3), or order[global thread index] with an order map.
+template <class Prob, int Method, bool kPilot = false>
 __global__ __launch_bounds__(kLdsStride)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void plain_kernel(typename Prob::Params prm, int64_t n,
                                                            const double* y0,  // may alias y1
@@ -809,10 +812,12 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void plain_kernel(
                                                            const double* __restrict__ g, Ctl c,
                                                            int32_t* __restrict__ status,
                                                            int32_t* __restrict__ stats,
-                                                           double* cols) {
+                                                           double* cols,
+                                                           const int32_t* __restrict__ order) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
-  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
-  if (i >= n) return;
+  const int64_t q = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
+  if (q >= n) return;
+  const int64_t i = order ? (int64_t)order[q] : q;
   integrate_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats,
                                  lane_slot<Prob, Method>(lds, cols));
 }
@@ -826,11 +831,13 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void plain_kernel(
 // step, instead of each new lane running them alone.  The lanes taking work
 // share one atomic add (wave-aggregated).  A lane retires once the queue is
 // exhausted; the loop ends when all the wave's lanes have retired, so every
-// wave leaves it.  Called by all 64 lanes of the wave.
+// wave leaves it.  Queue position q is system order[q] (q without a map).
+// Called by all 64 lanes of the wave.
 template <class Prob, int Method>
 __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, const double* y0,
                                 double* y1, const double* g, const Ctl& c, int32_t* status,
-                                int32_t* stats, unsigned long long* queue, double* slot) {
+                                int32_t* stats, unsigned long long* queue, double* slot,
+                                const int32_t* order) {
   const int lane = threadIdx.x;
   Driver<Prob, Method> D;
   int64_t i = -1;
@@ -851,7 +858,7 @@ __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, con
         const unsigned long long below = need_mask & ((1ull << lane) - 1ull);
         const unsigned long long idx = base + (unsigned long long)__popcll(below);
         if (idx < (unsigned long long)n) {
-          i = (int64_t)idx;
+          i = order ? (int64_t)order[idx] : (int64_t)idx;
           active = D.start(prm, c, n, i, y0, g, slot);
           if (!active) D.finish(n, i, y1, status, stats);
         } else {
@@ -868,8 +875,9 @@ __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, con
 }
 
 // Persistent kernel: a grid sized to the machine running persistent_loop over
-// the queue whose head, queue[0], must be zero at launch.
-template <class Prob, int Method>
+// the queue whose head, queue[0], must be zero at launch.  (kPilot only names
+// the instance a cost-order pilot runs, here and in plain_kernel.)
+template <class Prob, int Method, bool kPilot = false>
 __global__ __launch_bounds__(kLdsStride)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void persistent_kernel(typename Prob::Params prm,
                                                                 int64_t n, const double* y0,
@@ -878,10 +886,11 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void persistent_ke
                                                                 Ctl c, int32_t* __restrict__ status,
                                                                 int32_t* __restrict__ stats,
                                                                 unsigned long long* queue,
-                                                                double* cols) {
+                                                                double* cols,
+                                                                const int32_t* __restrict__ order) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   persistent_loop<Prob, Method>(prm, n, y0, y1, g, c, status, stats, queue,
-                                lane_slot<Prob, Method>(lds, cols));
+                                lane_slot<Prob, Method>(lds, cols), order);
 }
 
 }  // namespace rkmi

@@ -554,11 +554,12 @@ struct GDriver {
   __device__ void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
                          const Grp<GP>& x) const {
     const auto& y = D.state();
+    if (y1)
 #pragma unroll
-    for (int m = 0; m < GP::S; ++m) {
-      const int k = x.sp[m];
-      if (k >= 0) y1[(int64_t)k * n + i] = y[m];
-    }
+      for (int m = 0; m < GP::S; ++m) {
+        const int k = x.sp[m];
+        if (k >= 0) y1[(int64_t)k * n + i] = y[m];
+      }
     if (x.r == 0) {
       int32_t st[kNStats];
       D.stats(st);
@@ -599,7 +600,8 @@ constexpr int group_lds_doubles() {
 template <class GP, int Method>
 __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n, const double* y0,
                                       double* y1, const double* g, const Ctl& c, int32_t* status,
-                                      int32_t* stats, unsigned long long* queue, double* lds) {
+                                      int32_t* stats, unsigned long long* queue, double* lds,
+                                      const int32_t* order) {
   const int lane = threadIdx.x;
   const Grp<GP> x = group_of<GP>(lds);
   const int first_lane = lane - x.r;
@@ -623,7 +625,7 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
         const unsigned long long below = need_mask & ((1ull << first_lane) - 1ull);
         const unsigned long long idx = base + (unsigned long long)(__popcll(below) / GP::kL);
         if (idx < (unsigned long long)n) {
-          i = (int64_t)idx;
+          i = order ? (int64_t)order[idx] : (int64_t)idx;
           active = D.start(prm, c, n, i, y0, g, x);
           if (!active) D.finish(n, i, y1, status, stats, x);
         } else {
@@ -639,16 +641,16 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
   }
 }
 
-template <class GP, int Method>
+template <class GP, int Method, bool kPilot = false>
 __global__ __launch_bounds__(kLdsStride) void group_persistent_kernel(
     typename GP::Params prm, int64_t n, const double* y0, double* y1,
     const double* __restrict__ g, Ctl c, int32_t* __restrict__ status,
-    int32_t* __restrict__ stats, unsigned long long* queue) {
+    int32_t* __restrict__ stats, unsigned long long* queue, const int32_t* __restrict__ order) {
   __shared__ double lds[group_lds_doubles<GP>()];
-  group_persistent_loop<GP, Method>(prm, n, y0, y1, g, c, status, stats, queue, lds);
+  group_persistent_loop<GP, Method>(prm, n, y0, y1, g, c, status, stats, queue, lds, order);
 }
 
-template <class GP, int Method>
+template <class GP, int Method, bool kPilot>
 int launch_group_method(const LaunchArgs* a, hipStream_t s) {
   const int64_t units = (a->n + kGroups<GP> - 1) / kGroups<GP>;
   if (units <= 0) return kLaunchOk;
@@ -664,8 +666,8 @@ int launch_group_method(const LaunchArgs* a, hipStream_t s) {
   if (grid > units) grid = units;
   unsigned long long* queue = static_cast<unsigned long long*>(a->ws);
   queue_reset_kernel<><<<1, 1, 0, s>>>(queue);
-  group_persistent_kernel<GP, Method><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
-      a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue);
+  group_persistent_kernel<GP, Method, kPilot><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
+      a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, a->order);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
@@ -676,8 +678,11 @@ int launch_with_group(const LaunchArgs* a, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (a->schedule == kSchedPlain || a->schedule == kSchedPersistent) return launch<Prob>(a, stream);
   if (!a->ws || a->ws_bytes < kQueueBytes) return launch<Prob>(a, stream);   // no queue: plain
-  return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck>(a, s)
-                                  : launch_group_method<GP, kMethodRkc>(a, s);
+  if (a->pilot)
+    return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck, true>(a, s)
+                                    : launch_group_method<GP, kMethodRkc, true>(a, s);
+  return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck, false>(a, s)
+                                  : launch_group_method<GP, kMethodRkc, false>(a, s);
 }
 
 template <class Prob, class GP>

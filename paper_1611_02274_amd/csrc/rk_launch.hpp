@@ -62,7 +62,7 @@ int64_t workspace_bytes(int schedule, int64_t n) {
   return (int64_t)kQueueBytes + grid * (int64_t)block_col_bytes<Prob, Method>();
 }
 
-template <class Prob, int Method>
+template <class Prob, int Method, bool kPilot>
 int launch_method(const LaunchArgs* a, hipStream_t s) {
   const int64_t blocks = (a->n + kLdsStride - 1) / kLdsStride;
   if (blocks <= 0) return kLaunchOk;
@@ -81,8 +81,8 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
        ws_bytes >= kQueueBytes + col_bytes);
   if (!persistent) {
     if (col_bytes && ws_bytes < kQueueBytes + (size_t)blocks * col_bytes) return kLaunchWorkspace;
-    plain_kernel<Prob, Method><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
-        prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, cols);
+    plain_kernel<Prob, Method, kPilot><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, cols, a->order);
     return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
   }
   int64_t grid = 0;
@@ -95,16 +95,19 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
   }
   unsigned long long* queue = reinterpret_cast<unsigned long long*>(ws);
   queue_reset_kernel<><<<1, 1, 0, s>>>(queue);
-  persistent_kernel<Prob, Method><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
-      prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, cols);
+  persistent_kernel<Prob, Method, kPilot><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
+      prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, cols, a->order);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
 template <class Prob>
 int launch(const LaunchArgs* a, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  return a->method == kMethodRkck ? launch_method<Prob, kMethodRkck>(a, s)
-                                  : launch_method<Prob, kMethodRkc>(a, s);
+  if (a->pilot)
+    return a->method == kMethodRkck ? launch_method<Prob, kMethodRkck, true>(a, s)
+                                    : launch_method<Prob, kMethodRkc, true>(a, s);
+  return a->method == kMethodRkck ? launch_method<Prob, kMethodRkck, false>(a, s)
+                                  : launch_method<Prob, kMethodRkc, false>(a, s);
 }
 
 template <class Prob>

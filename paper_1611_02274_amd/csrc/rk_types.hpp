@@ -37,6 +37,9 @@ struct LaunchArgs {
   int32_t* stats;        // [kNStats][n] or null
   void* ws;              // workspace (may be null)
   size_t ws_bytes;
+  const int32_t* order;  // [n] queue position -> system index, or null (position = index)
+  int pilot;             // nonzero: a cost-order pilot (the same kernels under their own
+                         // names, so a profile tells the two passes apart)
 };
 
 // Enqueues the integration on the stream (a hipStream_t); 0 on success.

@@ -201,12 +201,16 @@ class Workload:
     atol: float
     seed: int
     T_range: tuple = (1000.0, 2500.0)
+    # keyword arguments of the integration call the benchmark times (schedule,
+    # cost order); tests that check the benchmark's launch use the same
+    launch: dict = dataclasses.field(default_factory=dict)
 
 
 WORKLOADS = {
-    "vdp4096_rkck": Workload("vdp4096_rkck", "rkck", "vdp", 4096, 0.0, 10.0, 1e-8, 1e-10, 1),
+    "vdp4096_rkck": Workload("vdp4096_rkck", "rkck", "vdp", 4096, 0.0, 10.0, 1e-8, 1e-10, 1,
+                             launch=dict(schedule=1)),
     "net13_rkc": Workload("net13_rkc", "rkc", "net13", 1 << 18, 0.0, 1e-6, 1e-8, 1e-12, 2002,
-                          (1000.0, 2500.0)),
+                          (1000.0, 2500.0), launch=dict(schedule=1, cost_order=1)),
     "net53_rkc": Workload("net53_rkc", "rkc", "net53", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3003,
                           (900.0, 2800.0)),
     "net53_rkck": Workload("net53_rkck", "rkck", "net53", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3003,

@@ -58,3 +58,24 @@ def test_batch_create_host_only():
     vdp = rk.Problem.vdp()
     arr1 = (C.c_void_p * 1)(vdp.handle.value)
     assert L.rk_batch_create(arr1, 1, C.byref(h)) == rk._lib.RK_EINVAL
+
+
+def test_cost_order_workspace_host_only():
+    """The cost order's workspace follows the integration's own (plain schedule
+    of a register-held network: none) at 256-byte alignment: pilot statistics
+    (6 int32 rows), the order map, a 4096-bucket histogram and its offsets."""
+    import ctypes as C
+
+    import paper_1611_02274_amd as rk
+    from paper_1611_02274_amd import _lib
+    L = _lib.lib()
+    p = rk.Problem.network(rk.inputs.standard_network(13))
+    a256 = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    for n in (1, 65, 1000, 262144):
+        o = rk._options(schedule=1)
+        assert L.rk_workspace_bytes(p.handle, _lib.RK_METHOD_RKC, n, C.byref(o)) == 0
+        o = rk._options(schedule=1, cost_order=1)
+        want = a256(6 * 4 * n) + a256(4 * n) + 2 * a256(4096 * 4)
+        assert L.rk_workspace_bytes(p.handle, _lib.RK_METHOD_RKC, n, C.byref(o)) == want
+    # max_steps, four int32 fields, cost_order, reserved[5]: the struct keeps its size
+    assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 + 4 * 5 == 48

@@ -158,7 +158,7 @@ def test_full_size_sampled(rk, orc, wname, n_sample):
     net = I.network_of(w.problem)
     y0, g = I.workload_inputs(w)
     prob, pb = rk.Problem.network(net), orc.network(net)
-    yg, sg, stg = _gpu(rk, w.method, prob, y0, g, w.t0, w.t1, w.rtol, w.atol)
+    yg, sg, stg = _gpu(rk, w.method, prob, y0, g, w.t0, w.t1, w.rtol, w.atol, **w.launch)
     idx = np.unique(np.linspace(0, w.n - 1, n_sample).astype(np.int64))
     yo, so, sto = _orc(orc, w.method, pb, np.ascontiguousarray(y0[:, idx]),
                        np.ascontiguousarray(g[:, idx]), w.t0, w.t1, w.rtol, w.atol)
@@ -213,8 +213,8 @@ def test_device_math_equals_host_and_oracle(rk, orc):
 ])
 def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
     """The plain, the persistent (queue-refilled) and the group (16 lanes per
-    system, for the 32- and 53-species networks) schedules give identical bits,
-    and all equal the oracle."""
+    system, for the 32- and 53-species networks) schedules, each with and
+    without the cost order, give identical bits, and all equal the oracle."""
     import torch
     say(f"case schedules {problem} {method} n={n}")
     if problem == "vdp":
@@ -224,7 +224,8 @@ def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
         net = I.network_of(problem)
         y0, g = I.kinetics_inputs(net, n, 21, T_range)
         prob, pb, atol = rk.Problem.network(net), orc.network(net), 1e-12
-    res = [_gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, atol, schedule=s) for s in (1, 2, 3)]
+    res = [_gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, atol, schedule=s, cost_order=co)
+           for co in (0, 1) for s in (1, 2, 3)]
     for other in res[1:]:
         for a, b in zip(res[0], other):
             assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
@@ -273,3 +274,47 @@ def test_column_workspace(rk, orc):
     assert call(1, plain) == _lib.RK_OK
     torch.cuda.synchronize()
     assert torch.equal(out, ref) and torch.equal(stats, stats_ref)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 4097])
+def test_cost_order_in_place(rk, orc, n):
+    """The cost order integrating in place (the pilot must leave y0 alone) over
+    ragged sizes, plain and persistent, equals the oracle."""
+    import torch
+    say(f"case cost order in place n={n}")
+    net = I.network_of("net13")
+    y0, g = I.kinetics_inputs(net, n, 31, (1000.0, 2500.0))
+    prob = rk.Problem.network(net)
+    yo, so, sto = _orc(orc, "rkc", orc.network(net), y0, g, 0.0, 2e-7, 1e-8, 1e-12)
+    for s in (1, 2):
+        yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+        y1, st, stats = rk.integrate_rkc(prob, yd, gd, 0.0, 2e-7, 1e-8, 1e-12, out=yd,
+                                         schedule=s, cost_order=1)
+        torch.cuda.synchronize()
+        assert y1.data_ptr() == yd.data_ptr()
+        compare(y1.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy(), yo, so, sto, 1e-12,
+                f"cost order in place s={s} n={n}")
+
+
+def test_cost_order_rejects(rk):
+    """The cost order needs its workspace and is refused for a taped integration."""
+    import ctypes as C
+
+    import torch
+    from paper_1611_02274_amd import _lib
+    L = _lib.lib()
+    net = I.network_of("net13")
+    y0, g = I.kinetics_inputs(net, 100, 1, (1000.0, 2500.0))
+    prob = rk.Problem.network(net)
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    out = torch.empty_like(yd)
+    o = rk._options(schedule=1, cost_order=1)
+    need = L.rk_workspace_bytes(prob.handle, _lib.RK_METHOD_RKC, 100, C.byref(o))
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    f = L.rk_integrate_rkc
+    assert f(prob.handle, 100, yd.data_ptr(), out.data_ptr(), gd.data_ptr(), 0.0, 1e-7, 1e-8,
+             1e-12, None, None, ws.data_ptr(), need - 256, C.byref(o), s) == _lib.RK_EWORKSPACE
+    assert f(prob.handle, 100, yd.data_ptr(), out.data_ptr(), gd.data_ptr(), 0.0, 1e-7, 1e-8,
+             1e-12, None, None, ws.data_ptr(), need, C.byref(o), s) == _lib.RK_OK
+    torch.cuda.synchronize()
