@@ -81,11 +81,27 @@ __device__ inline int order_bucket(const int32_t* __restrict__ pstats, int64_t n
   return c < 0 ? 0 : (c >= kOrderBuckets ? kOrderBuckets - 1 : (int)c);
 }
 
+// Systems per workgroup of the histogram and scatter kernels: each workgroup
+// counts its chunk in LDS first, so a bucket takes one global atomic per
+// workgroup rather than one per system.
+constexpr int kOrderChunkThreads = 256;
+constexpr int kOrderChunkPerThread = 16;
+constexpr int kOrderChunk = kOrderChunkThreads * kOrderChunkPerThread;
+
 template <int = 0>
-__global__ void order_hist_kernel(const int32_t* __restrict__ pstats, int64_t n,
-                                  int32_t* __restrict__ hist) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&hist[order_bucket(pstats, n, i)], 1);
+__global__ __launch_bounds__(kOrderChunkThreads) void order_hist_kernel(
+    const int32_t* __restrict__ pstats, int64_t n, int32_t* __restrict__ hist) {
+  __shared__ int32_t cnt[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderChunkThreads) cnt[b] = 0;
+  __syncthreads();
+  const int64_t first = (int64_t)blockIdx.x * kOrderChunk;
+  for (int k = 0; k < kOrderChunkPerThread; ++k) {
+    const int64_t i = first + (int64_t)k * kOrderChunkThreads + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[order_bucket(pstats, n, i)], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderChunkThreads)
+    if (cnt[b]) atomicAdd(&hist[b], cnt[b]);
 }
 
 // offs[b] = number of systems whose bucket is above b (one workgroup).
@@ -114,11 +130,34 @@ __global__ __launch_bounds__(kOrderScanThreads) void order_scan_kernel(
   }
 }
 
+// Each workgroup ranks its chunk's systems within their buckets in LDS,
+// reserves one range per bucket from the running offsets, and writes the
+// systems' indices there.
 template <int = 0>
-__global__ void order_scatter_kernel(const int32_t* __restrict__ pstats, int64_t n,
-                                     int32_t* __restrict__ offs, int32_t* __restrict__ order) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) order[atomicAdd(&offs[order_bucket(pstats, n, i)], 1)] = (int32_t)i;
+__global__ __launch_bounds__(kOrderChunkThreads) void order_scatter_kernel(
+    const int32_t* __restrict__ pstats, int64_t n, int32_t* __restrict__ offs,
+    int32_t* __restrict__ order) {
+  __shared__ int32_t cnt[kOrderBuckets];
+  __shared__ int32_t base[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderChunkThreads) cnt[b] = 0;
+  __syncthreads();
+  const int64_t first = (int64_t)blockIdx.x * kOrderChunk;
+  int bucket[kOrderChunkPerThread], rank[kOrderChunkPerThread];
+#pragma unroll
+  for (int k = 0; k < kOrderChunkPerThread; ++k) {
+    const int64_t i = first + (int64_t)k * kOrderChunkThreads + threadIdx.x;
+    bucket[k] = i < n ? order_bucket(pstats, n, i) : -1;
+    rank[k] = bucket[k] >= 0 ? atomicAdd(&cnt[bucket[k]], 1) : 0;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kOrderBuckets; b += kOrderChunkThreads)
+    base[b] = cnt[b] ? atomicAdd(&offs[b], cnt[b]) : 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kOrderChunkPerThread; ++k) {
+    const int64_t i = first + (int64_t)k * kOrderChunkThreads + threadIdx.x;
+    if (bucket[k] >= 0) order[base[bucket[k]] + rank[k]] = (int32_t)i;
+  }
 }
 
 // Enqueues the pilot through `launch` (the problem's launcher), the sort,
@@ -147,11 +186,11 @@ int launch_cost_ordered(const LaunchArgs* a, size_t base_bytes, LaunchFn launch,
   p.pilot = 1;
   int rc = launch(&p, stream);
   if (rc) return rc;
-  const unsigned blocks = (unsigned)((a->n + 255) / 256);
+  const unsigned chunks = (unsigned)((a->n + kOrderChunk - 1) / kOrderChunk);
   order_clear_kernel<><<<1, 256, 0, s>>>(hist);
-  order_hist_kernel<><<<blocks, 256, 0, s>>>(pstats, a->n, hist);
+  order_hist_kernel<><<<chunks, kOrderChunkThreads, 0, s>>>(pstats, a->n, hist);
   order_scan_kernel<><<<1, kOrderScanThreads, 0, s>>>(hist, offs);
-  order_scatter_kernel<><<<blocks, 256, 0, s>>>(pstats, a->n, offs, order);
+  order_scatter_kernel<><<<chunks, kOrderChunkThreads, 0, s>>>(pstats, a->n, offs, order);
   if (hipGetLastError() != hipSuccess) return kLaunchHip;
   LaunchArgs m = *a;
   m.ws_bytes = base_bytes;
