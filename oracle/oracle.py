@@ -81,6 +81,15 @@ def lib():
             "orc_rkc_adjoint_batch": (C.c_int, [P, C.c_int64, _dp, _dp, C.c_double, C.c_double,
                                                 C.c_double, C.c_double, C.c_int64, _dp, _dp, _dp,
                                                 _dp, _ip, C.c_int]),
+            "orc_rkck_adjoint_batch": (C.c_int, [P, C.c_int64, _dp, _dp, C.c_double, C.c_double,
+                                                 C.c_double, C.c_double, C.c_int64, _dp, _dp,
+                                                 _dp, _dp, _ip, C.c_int]),
+            "orc_rkck_solve_rec": (C.c_int, [P, _dp, _dp, _dp, C.c_double, C.c_double,
+                                             C.c_double, C.c_double, C.c_int64, _ip, _dp,
+                                             C.c_int64, C.POINTER(C.c_int64)]),
+            "orc_rkck_replay": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _dp]),
+            "orc_rkck_replay_adjoint": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _dp,
+                                                  _dp, _dp]),
             "orc_max_threads": (C.c_int, []),
             "orc_cr_exp": (C.c_double, [C.c_double]),
             "orc_cr_log": (C.c_double, [C.c_double]),
@@ -275,6 +284,35 @@ def rkc_solve(pb, g, y0, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, rec_ca
     return y1, rc, st, rh[:n].copy(), rs[:n].copy()
 
 
+def rkck_solve_rec(pb, g, y0, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, rec_cap=1 << 20):
+    """RKCK as rkck_solve; returns (y1, status, stats, h_steps) with the accepted steps."""
+    y0 = _vec(y0, pb.n_eq)
+    y1 = np.zeros(pb.n_eq)
+    st = np.zeros(NSTATS, dtype=np.int32)
+    rh = np.zeros(rec_cap)
+    nrec = C.c_int64(0)
+    rc = lib().orc_rkck_solve_rec(pb.ptr, _d(_g(pb, g)), _d(y0), _d(y1), t0, t1, rtol, atol,
+                                  max_steps, _i(st), _d(rh), rec_cap, C.byref(nrec))
+    assert rc >= 0, rc
+    return y1, rc, st, rh[:min(nrec.value, rec_cap)].copy()
+
+
+def rkck_replay(pb, g, y0, t0, h):
+    y0, h = _vec(y0, pb.n_eq), _vec(h)
+    y1 = np.zeros(pb.n_eq)
+    assert lib().orc_rkck_replay(pb.ptr, _d(_g(pb, g)), _d(y0), t0, h.size, _d(h), _d(y1)) == 0
+    return y1
+
+
+def rkck_replay_adjoint(pb, g, y0, t0, h, w):
+    y0, w, h = _vec(y0, pb.n_eq), _vec(w, pb.n_eq), _vec(h)
+    dy0 = np.zeros(pb.n_eq)
+    dth = np.zeros(max(pb.n_theta, 1))
+    assert lib().orc_rkck_replay_adjoint(pb.ptr, _d(_g(pb, g)), _d(y0), t0, h.size, _d(h),
+                                         _d(w), _d(dy0), _d(dth)) == 0
+    return dy0, dth[:pb.n_theta]
+
+
 def rkc_replay(pb, g, y0, t0, h, s):
     y0 = _vec(y0, pb.n_eq)
     h = _vec(h)
@@ -332,6 +370,23 @@ def rkc_adjoint_batch(pb, y0, g, w, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_ST
     status = np.zeros(n, dtype=np.int32)
     rc = lib().orc_rkc_adjoint_batch(pb.ptr, n, _d(y0), _d(g), t0, t1, rtol, atol, max_steps,
                                      _d(w), _d(y1), _d(dy0), _d(dth), _i(status), n_threads)
+    assert rc == 0, rc
+    return y1, dy0, dth[:pb.n_theta], status
+
+
+def rkck_adjoint_batch(pb, y0, g, w, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS,
+                       n_threads=0):
+    """Forward RKCK and the discrete adjoint of its accepted steps, as
+    rkc_adjoint_batch."""
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = y0.shape[1]
+    y1, dy0 = np.zeros_like(y0), np.zeros_like(y0)
+    dth = np.zeros((max(pb.n_theta, 1), n))
+    status = np.zeros(n, dtype=np.int32)
+    rc = lib().orc_rkck_adjoint_batch(pb.ptr, n, _d(y0), _d(g), t0, t1, rtol, atol, max_steps,
+                                      _d(w), _d(y1), _d(dy0), _d(dth), _i(status), n_threads)
     assert rc == 0, rc
     return y1, dy0, dth[:pb.n_theta], status
 

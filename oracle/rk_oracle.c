@@ -271,17 +271,21 @@ void orc_rkck_tableau(double a[6], double b[36], double c[6], double cs[6], doub
 /* One RKCK trial step (Sec. 2.1 stage equations): k_1 = h F with F = f(t, y)
  * supplied; k_i = h f(t + a_i h, y + sum_{j<i} b_ij k_j); the fifth-order
  * solution y + sum c_i k_i and the error estimate sum (c_i - c*_i) k_i. */
-static void rkck_trial(const orc_sys *S, double t, const double *y, const double *F, double h,
-                       double *ytemp, double *yerr) {
+static void rkck_trial_z(const orc_sys *S, double t, const double *y, const double *F, double h,
+                         double *ytemp, double *yerr, double *zst) {
   const int N = S->pb->n_eq;
   double k[6][ORC_MAXN], z[ORC_MAXN], f[ORC_MAXN];
   for (int i = 0; i < N; ++i) k[0][i] = h * F[i];
+  if (zst)
+    for (int i = 0; i < N; ++i) zst[i] = y[i];
   for (int s = 1; s < 6; ++s) {
     for (int i = 0; i < N; ++i) {
       double acc = y[i];
       for (int j = 0; j < s; ++j) acc = acc + RKCK_B[s][j] * k[j][i];
       z[i] = acc;
     }
+    if (zst)
+      for (int i = 0; i < N; ++i) zst[(size_t)s * N + i] = z[i];
     rhs(S, t + RKCK_A[s] * h, z, f);
     for (int i = 0; i < N; ++i) k[s][i] = h * f[i];
   }
@@ -297,6 +301,11 @@ static void rkck_trial(const orc_sys *S, double t, const double *y, const double
       if (RKCK_E[s] != 0.0) e = e + RKCK_E[s] * k[s][i];
     yerr[i] = e;
   }
+}
+
+static void rkck_trial(const orc_sys *S, double t, const double *y, const double *F, double h,
+                       double *ytemp, double *yerr) {
+  rkck_trial_z(S, t, y, F, h, ytemp, yerr, NULL);
 }
 
 int orc_rkck_trial(const orc_problem *pb, const double *g, double t, const double *y,
@@ -349,15 +358,41 @@ double orc_rkck_control(double err, int nan_flag, double h, double hmin, double 
   return fmax(hmin, fmin(hmax, hn));
 }
 
+/* Record of the accepted steps of one integration: (h, s) per step; grows by
+ * realloc when `grow` is set, else keeps the first cap steps and counts the rest. */
+typedef struct {
+  double *h;
+  int32_t *s;
+  int64_t n, cap;
+  int grow; /* 1: realloc as needed */
+} step_rec;
+
+static void rec_push(step_rec *r, double h, int s) {
+  if (!r) return;
+  if (r->n >= r->cap && r->grow) {
+    int64_t nc = r->cap ? 2 * r->cap : 256;
+    double *nh = (double *)realloc(r->h, sizeof(double) * nc);
+    if (nh) r->h = nh;
+    int32_t *ns = (int32_t *)realloc(r->s, sizeof(int32_t) * nc);
+    if (ns) r->s = ns;
+    if (nh && ns) r->cap = nc;
+  }
+  if (r->n < r->cap && r->h && r->s) {
+    r->h[r->n] = h;
+    r->s[r->n] = s;
+  }
+  r->n++;
+}
+
 /* RKCK driver (Sec. 3.1): hMax = |t1 - t0|, hMin = 1e-20, first trial step
  * half the interval; loop until t reaches t1, clipping the step to the time
  * left.  Reading: f(t, y) is kept after a rejection (same arguments, same
  * value) instead of being evaluated again; guards stop a system whose step
  * falls below hMin after a rejection, whose accepted state is not finite, or
  * that exhausts max_steps attempts (the listing has no exit for these). */
-int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, double *y1,
-                   double t0, double t1, double rtol, double atol, int64_t max_steps,
-                   int32_t *stats) {
+static int rkck_solve_impl(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                           double t0, double t1, double rtol, double atol, int64_t max_steps,
+                           int32_t *stats, step_rec *rec) {
   if (check_problem(pb) || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
   if (!S) return -2;
@@ -396,6 +431,7 @@ int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, dou
         break;
       }
     } else {
+      rec_push(rec, h, 6);
       t += h;
       h = hnew;
       for (int i = 0; i < N; ++i) y[i] = ytemp[i];
@@ -418,6 +454,25 @@ int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, dou
   }
   free(S);
   return status;
+}
+
+int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                   double t0, double t1, double rtol, double atol, int64_t max_steps,
+                   int32_t *stats) {
+  return rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, NULL);
+}
+
+/* As orc_rkck_solve, also recording the accepted step sizes (the first
+ * rec_cap of them; *n_rec receives the count). */
+int orc_rkck_solve_rec(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                       double t0, double t1, double rtol, double atol, int64_t max_steps,
+                       int32_t *stats, double *rec_h, int64_t rec_cap, int64_t *n_rec) {
+  int32_t *rs = rec_h && rec_cap > 0 ? (int32_t *)malloc(sizeof(int32_t) * (size_t)rec_cap) : NULL;
+  step_rec r = {rec_h, rs, 0, rs ? rec_cap : 0, 0};
+  int st = rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r);
+  if (n_rec) *n_rec = r.n;
+  free(rs);
+  return st;
 }
 
 /* ====================================================================== RKC */
@@ -688,30 +743,6 @@ double orc_rkc_accept_factor(double err, double err_prev, double h, double h_pre
   return fac;
 }
 
-typedef struct {
-  double *h;
-  int32_t *s;
-  int64_t n, cap;
-  int grow; /* 1: realloc as needed */
-} rkc_rec;
-
-static void rec_push(rkc_rec *r, double h, int s) {
-  if (!r) return;
-  if (r->n >= r->cap && r->grow) {
-    int64_t nc = r->cap ? 2 * r->cap : 256;
-    double *nh = (double *)realloc(r->h, sizeof(double) * nc);
-    if (nh) r->h = nh;
-    int32_t *ns = (int32_t *)realloc(r->s, sizeof(int32_t) * nc);
-    if (ns) r->s = ns;
-    if (nh && ns) r->cap = nc;
-  }
-  if (r->n < r->cap && r->h && r->s) {
-    r->h[r->n] = h;
-    r->s[r->n] = s;
-  }
-  r->n++;
-}
-
 /* RKC driver (Sec. 3.2 listing, Sec. 2.2 equations).
  * Reading (restart): every call starts fresh, with the previous-step memory
  * cleared and the eigenvector estimate v set to f(t0, y0); the listing's test
@@ -724,7 +755,7 @@ static void rec_push(rkc_rec *r, double h, int s) {
  * Guards as in the RKCK driver. */
 static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *y0, double *y1,
                           double t0, double t1, double rtol, double atol, int64_t max_steps,
-                          int32_t *stats, rkc_rec *rec) {
+                          int32_t *stats, step_rec *rec) {
   if (check_problem(pb) || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq;
   const int mmax = orc_rkc_mmax(rtol);
@@ -859,7 +890,7 @@ int orc_rkc_solve(const orc_problem *pb, const double *g, const double *y0, doub
                   double t0, double t1, double rtol, double atol, int64_t max_steps,
                   int32_t *stats, double *rec_h, int32_t *rec_s, int64_t rec_cap,
                   int64_t *n_rec) {
-  rkc_rec r = {rec_h, rec_s, 0, (rec_h && rec_s) ? rec_cap : 0, 0};
+  step_rec r = {rec_h, rec_s, 0, (rec_h && rec_s) ? rec_cap : 0, 0};
   int st = rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r);
   if (n_rec) *n_rec = r.n;
   return st;
@@ -985,6 +1016,91 @@ int orc_rkc_replay_adjoint(const orc_problem *pb, const double *g, const double 
   return 0;
 }
 
+/* Replay of recorded RKCK steps: the fifth-order solution of each trial step
+ * (Sec. 2.1) with the recorded step sizes, no error control. */
+int orc_rkck_replay(const orc_problem *pb, const double *g, const double *y0, double t0,
+                    int64_t n_steps, const double *h, double *y1) {
+  if (check_problem(pb)) return -1;
+  const int N = pb->n_eq;
+  orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
+  if (!S) return -2;
+  sys_init(S, pb, g);
+  double y[ORC_MAXN], F[ORC_MAXN], yt[ORC_MAXN], ye[ORC_MAXN];
+  for (int i = 0; i < N; ++i) y[i] = y0[i];
+  double t = t0;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    rhs(S, t, y, F);
+    rkck_trial(S, t, y, F, h[k], yt, ye);
+    for (int i = 0; i < N; ++i) y[i] = yt[i];
+    t += h[k];
+  }
+  for (int i = 0; i < N; ++i) y1[i] = y[i];
+  free(S);
+  return 0;
+}
+
+/* Discrete adjoint of the RKCK accepted-step map with the step sizes held
+ * fixed.  One step (Sec. 2.1 stage equations, Table 1 coefficients) is
+ *   z_1 = y,  z_i = y + sum_{j<i} b_ij k_j,  k_i = h f(z_i),  y' = y + sum_i c_i k_i,
+ * so for lambda = dL/dy' its transpose is
+ *   kbar_i = c_i lambda,  ybar = lambda;  for i = 6..1:
+ *     u = h kbar_i,  zbar = J(z_i)^T u,  thetabar += (df/dtheta)(z_i)^T u,
+ *     ybar += zbar,  kbar_j += b_ij zbar (j < i);
+ * and ybar is lambda for the step before.  Every step-start state is stored
+ * and each step's stage states are recomputed (no checkpoints). */
+int orc_rkck_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
+                            double t0, int64_t n_steps, const double *h, const double *w,
+                            double *dy0, double *dtheta) {
+  if (check_problem(pb)) return -1;
+  const int N = pb->n_eq;
+  const int NT = orc_n_theta(pb);
+  orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
+  double *Y = (double *)malloc(sizeof(double) * (size_t)(n_steps + 1) * N);
+  double *tk = (double *)malloc(sizeof(double) * (size_t)(n_steps + 1));
+  if (!S || !Y || !tk) {
+    free(S); free(Y); free(tk);
+    return -2;
+  }
+  sys_init(S, pb, g);
+  double F[ORC_MAXN], yt[ORC_MAXN], ye[ORC_MAXN], Z[6 * ORC_MAXN];
+  double lam[ORC_MAXN], yb[ORC_MAXN], kb[6][ORC_MAXN], u[ORC_MAXN], jtu[ORC_MAXN];
+  double th[ORC_MAXR + 1], thacc[ORC_MAXR + 1];
+  for (int i = 0; i < N; ++i) Y[i] = y0[i];
+  tk[0] = t0;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    const double *yk = Y + (size_t)k * N;
+    rhs(S, tk[k], yk, F);
+    rkck_trial(S, tk[k], yk, F, h[k], yt, ye);
+    for (int i = 0; i < N; ++i) Y[(size_t)(k + 1) * N + i] = yt[i];
+    tk[k + 1] = tk[k] + h[k];
+  }
+  for (int i = 0; i < N; ++i) lam[i] = w[i];
+  for (int q = 0; q < NT; ++q) thacc[q] = 0.0;
+  for (int64_t k = n_steps - 1; k >= 0; --k) {
+    const double hk = h[k];
+    const double *yk = Y + (size_t)k * N;
+    rhs(S, tk[k], yk, F);
+    rkck_trial_z(S, tk[k], yk, F, hk, yt, ye, Z);
+    for (int st = 0; st < 6; ++st)
+      for (int i = 0; i < N; ++i) kb[st][i] = RKCK_C[st] * lam[i];
+    for (int i = 0; i < N; ++i) yb[i] = lam[i];
+    for (int st = 5; st >= 0; --st) {
+      for (int i = 0; i < N; ++i) u[i] = hk * kb[st][i];
+      rhs_vjp(S, Z + (size_t)st * N, u, jtu, th);
+      for (int q = 0; q < NT; ++q) thacc[q] += th[q];
+      for (int i = 0; i < N; ++i) yb[i] += jtu[i];
+      for (int j = 0; j < st; ++j)
+        for (int i = 0; i < N; ++i) kb[j][i] += RKCK_B[st][j] * jtu[i];
+    }
+    for (int i = 0; i < N; ++i) lam[i] = yb[i];
+  }
+  for (int i = 0; i < N; ++i) dy0[i] = lam[i];
+  if (dtheta)
+    for (int q = 0; q < NT; ++q) dtheta[q] = thacc[q];
+  free(S); free(Y); free(tk);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ batches */
 
 int orc_max_threads(void) {
@@ -1065,10 +1181,46 @@ int orc_rkc_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, co
     gather(y0, n, i, N, ys);
     gather(g, n, i, P, gs);
     gather(w, n, i, N, ws);
-    rkc_rec r = {NULL, NULL, 0, 0, 1};
+    step_rec r = {NULL, NULL, 0, 0, 1};
     int rc = rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r);
     int rc2 = (rc >= 0 && r.n <= r.cap)
                   ? orc_rkc_replay_adjoint(pb, gs, ys, t0, r.n, r.h, r.s, ws, d0, dth)
+                  : -2;
+    free(r.h);
+    free(r.s);
+    if (rc < 0 || rc2 < 0) {
+#pragma omp atomic write
+      failed = 1;
+      continue;
+    }
+    scatter(y1, n, i, N, yo);
+    scatter(dy0, n, i, N, d0);
+    if (dtheta) scatter(dtheta, n, i, NT, dth);
+    if (status) status[i] = rc;
+  }
+  return failed ? -2 : 0;
+}
+
+int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                           double t0, double t1, double rtol, double atol, int64_t max_steps,
+                           const double *w, double *y1, double *dy0, double *dtheta,
+                           int32_t *status, int n_threads) {
+  if (check_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
+  const int N = pb->n_eq, P = pb->n_param, NT = orc_n_theta(pb);
+  int nt = n_threads > 0 ? n_threads : orc_max_threads();
+  int failed = 0;
+  (void)nt;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+  for (int64_t i = 0; i < n; ++i) {
+    double ys[ORC_MAXN], yo[ORC_MAXN], gs[ORC_MAXP], ws[ORC_MAXN], d0[ORC_MAXN];
+    double dth[ORC_MAXR + 1];
+    gather(y0, n, i, N, ys);
+    gather(g, n, i, P, gs);
+    gather(w, n, i, N, ws);
+    step_rec r = {NULL, NULL, 0, 0, 1};
+    int rc = rkck_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r);
+    int rc2 = (rc >= 0 && r.n <= r.cap)
+                  ? orc_rkck_replay_adjoint(pb, gs, ys, t0, r.n, r.h, ws, d0, dth)
                   : -2;
     free(r.h);
     free(r.s);

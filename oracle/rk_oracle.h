@@ -98,6 +98,11 @@ double orc_rkc_accept_factor(double err, double err_prev, double h, double h_pre
 int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, double *y1,
                    double t0, double t1, double rtol, double atol, int64_t max_steps,
                    int32_t *stats);
+/* As orc_rkck_solve; rec_h (capacity rec_cap) receives the accepted steps'
+ * sizes, *n_rec their number (may exceed rec_cap: not stored). */
+int orc_rkck_solve_rec(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                       double t0, double t1, double rtol, double atol, int64_t max_steps,
+                       int32_t *stats, double *rec_h, int64_t rec_cap, int64_t *n_rec);
 /* rec_h / rec_s (capacity rec_cap, may be NULL) receive the accepted steps'
  * size and stage count; *n_rec their number (may exceed rec_cap: not stored). */
 int orc_rkc_solve(const orc_problem *pb, const double *g, const double *y0, double *y1,
@@ -112,6 +117,13 @@ int orc_rkc_replay(const orc_problem *pb, const double *g, const double *y0, dou
 int orc_rkc_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
                            double t0, int64_t n_steps, const double *h, const int32_t *s,
                            const double *w, double *dy0, double *dtheta);
+/* Replays accepted RKCK steps h_k from y0 with no controller. */
+int orc_rkck_replay(const orc_problem *pb, const double *g, const double *y0, double t0,
+                    int64_t n_steps, const double *h, double *y1);
+/* Discrete adjoint of the replayed RKCK step map for L = w . y(t1). */
+int orc_rkck_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
+                            double t0, int64_t n_steps, const double *h, const double *w,
+                            double *dy0, double *dtheta);
 
 /* ---- batches (SoA), OpenMP across systems; n_threads <= 0: runtime default ---- */
 int orc_rkck_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
@@ -125,6 +137,11 @@ int orc_rkc_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, co
                           double t0, double t1, double rtol, double atol, int64_t max_steps,
                           const double *w, double *y1, double *dy0, double *dtheta,
                           int32_t *status, int n_threads);
+/* forward RKCK + adjoint per system, as orc_rkc_adjoint_batch */
+int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                           double t0, double t1, double rtol, double atol, int64_t max_steps,
+                           const double *w, double *y1, double *dy0, double *dtheta,
+                           int32_t *status, int n_threads);
 int orc_max_threads(void);
 
 #ifdef __cplusplus

@@ -114,3 +114,131 @@ def test_adjoint_batch_matches_single(orc):
         _, _, _, hs, ss = orc.rkc_solve(pb, g[:, i], y0[:, i], 0.0, 2e-8, 1e-8, 1e-12)
         d0, dl = orc.rkc_replay_adjoint(pb, g[:, i], y0[:, i], 0.0, hs, ss, w[:, i])
         assert np.array_equal(d0, dy0[:, i]) and np.array_equal(dl, dth[:, i])
+
+
+# ------------------------------------------------------------------ RKCK
+def _rkck_R(z):
+    """Stability function of the Cash-Karp fifth-order solution at z (complex
+    or real): R(z) = 1 + z c^T (I - z B)^{-1} 1 with the Table 1 stage matrix B
+    and weights c, as a linear solve (the tableau itself is pinned by the
+    order conditions in test_oracle_rkck)."""
+    from oracle import oracle as orc
+    a, B, c, cs, e = orc.rkck_tableau()
+    Bm = np.zeros((6, 6))
+    for i in range(6):
+        for j in range(i):
+            Bm[i, j] = B[i, j]
+    return 1.0 + z * (c @ np.linalg.solve(np.eye(6) - z * Bm, np.ones(6)))
+
+
+def test_rkck_replay_reproduces_solve(orc):
+    """The recorded step sizes replayed without a controller give the solve's
+    final state bit for bit (van der Pol and the 13-species network)."""
+    pb = orc.vdp()
+    y1, st, _, hs = orc.rkck_solve_rec(pb, [1.3], [1.0, -0.5], 0.0, 2.0, 1e-8, 1e-10)
+    assert st == orc.OK and len(hs) > 10
+    assert np.array_equal(orc.rkck_replay(pb, [1.3], [1.0, -0.5], 0.0, hs), y1)
+    net = I.standard_network(13)
+    pn = orc.network(net)
+    y0, g = I.kinetics_inputs(net, 1, 7)
+    y1, st, stats, hs = orc.rkck_solve_rec(pn, g[:, 0], y0[:, 0], 0.0, 5e-8, 1e-8, 1e-12)
+    assert st == orc.OK and len(hs) == stats[0] > 5
+    assert np.array_equal(orc.rkck_replay(pn, g[:, 0], y0[:, 0], 0.0, hs), y1)
+
+
+def test_rkck_scalar_linear_closed_form(orc):
+    """y' = lam y: each step multiplies by R(h lam), so dL/dy0 = w prod_k R(h_k lam)."""
+    lam = -3.0
+    pb = orc.linear([[lam]])
+    y1, st, _, hs = orc.rkck_solve_rec(pb, None, [1.0], 0.0, 2.0, 1e-9, 1e-12)
+    assert st == orc.OK and len(hs) > 5
+    prod = np.prod([_rkck_R(h * lam) for h in hs])
+    dy0, _ = orc.rkck_replay_adjoint(pb, None, [1.0], 0.0, hs, [0.7])
+    assert dy0[0] == pytest.approx(0.7 * prod, rel=1e-12)
+    assert y1[0] == pytest.approx(prod, rel=1e-12)
+
+
+def test_rkck_matrix_linear_closed_form(orc):
+    """y' = A y (symmetric A): the step map is R(h A), so
+    dL/dy0 = (prod_k R(h_k A))^T w, evaluated in the eigenbasis; a transposed
+    or dropped stage coupling changes the product's off-diagonal action."""
+    eigs = [-0.5, -3.0, -20.0, -60.0]
+    A = I.linear_problem_matrix(eigs, seed=4)
+    pb = orc.linear(A)
+    y0 = np.array([0.3, -1.0, 0.5, 2.0])
+    y1, st, _, hs = orc.rkck_solve_rec(pb, None, y0, 0.0, 1.0, 1e-9, 1e-12)
+    assert st == orc.OK and len(hs) > 5
+    lam, Q = np.linalg.eigh(A)
+    m = np.ones(len(eigs))
+    for h in hs:
+        m *= np.array([_rkck_R(h * l) for l in lam])
+    M = Q @ np.diag(m) @ Q.T
+    w = np.array([1.0, 0.2, -0.4, 0.9])
+    dy0, _ = orc.rkck_replay_adjoint(pb, None, y0, 0.0, hs, w)
+    assert np.allclose(dy0, M.T @ w, rtol=1e-10, atol=1e-13)
+    assert np.allclose(y1, M @ y0, rtol=1e-10, atol=1e-13)
+
+
+def _loss_ck(orc, pb, g, y0, hs, w):
+    return float(w @ orc.rkck_replay(pb, g, y0, 0.0, hs))
+
+
+def test_rkck_vdp_adjoint_vs_fd(orc):
+    pb = orc.vdp()
+    mu, y0 = np.array([1.3]), np.array([1.0, -0.5])
+    _, st, _, hs = orc.rkck_solve_rec(pb, mu, y0, 0.0, 2.0, 1e-7, 1e-9)
+    w = np.array([0.4, -1.1])
+    dy0, dmu = orc.rkck_replay_adjoint(pb, mu, y0, 0.0, hs, w)
+    e = 1e-6
+    for m in range(2):
+        d = np.zeros(2)
+        d[m] = e
+        fd = (_loss_ck(orc, pb, mu, y0 + d, hs, w) - _loss_ck(orc, pb, mu, y0 - d, hs, w)) / (2 * e)
+        assert dy0[m] == pytest.approx(fd, rel=1e-7)
+    fd = (_loss_ck(orc, pb, mu + e, y0, hs, w) - _loss_ck(orc, pb, mu - e, y0, hs, w)) / (2 * e)
+    assert dmu[0] == pytest.approx(fd, rel=1e-7)
+
+
+def test_rkck_network_adjoint_vs_fd(orc):
+    """13-species network under RKCK: dL/dY0 and dL/dlnA against central
+    differences of the replayed steps, normwise as for RKC."""
+    net = I.standard_network(13)
+    pb = orc.network(net)
+    y0, g = I.kinetics_inputs(net, 1, 5006)
+    w = I.adjoint_weights(13, 1, 5006)
+    yi, gi, wi = y0[:, 0], g[:, 0], w[:, 0]
+    _, st, _, hs = orc.rkck_solve_rec(pb, gi, yi, 0.0, 5e-8, 1e-8, 1e-12)
+    assert st == orc.OK and len(hs) > 10
+    dy0, dlnA = orc.rkck_replay_adjoint(pb, gi, yi, 0.0, hs, wi)
+    e = 1e-6
+    fd_y = np.empty(13)
+    for m in range(13):
+        d = np.zeros(13)
+        d[m] = e
+        fd_y[m] = (_loss_ck(orc, pb, gi, yi + d, hs, wi) - _loss_ck(orc, pb, gi, yi - d, hs, wi)) / (2 * e)
+    assert np.abs(dy0 - fd_y).max() <= 1e-6 * np.abs(fd_y).max()
+    cols = np.arange(0, net.n_rx, 2)
+    fd_a = np.empty(len(cols))
+    for c, j in enumerate(cols):
+        d = np.zeros(net.n_rx)
+        d[j] = e
+        fp = _loss_ck(orc, pb.with_lnA(net.lnA + d), gi, yi, hs, wi)
+        fm = _loss_ck(orc, pb.with_lnA(net.lnA - d), gi, yi, hs, wi)
+        fd_a[c] = (fp - fm) / (2 * e)
+    assert np.abs(dlnA[cols] - fd_a).max() <= 1e-6 * np.abs(fd_a).max()
+    big = np.abs(fd_a) > 1e-2 * np.abs(fd_a).max()
+    np.testing.assert_allclose(dlnA[cols][big], fd_a[big], rtol=1e-5)
+
+
+def test_rkck_adjoint_batch_matches_single(orc):
+    net = I.standard_network(9)
+    pb = orc.network(net)
+    y0, g = I.kinetics_inputs(net, 3, 77, (800.0, 3000.0))
+    w = I.adjoint_weights(9, 3, 77)
+    y1, dy0, dth, status = orc.rkck_adjoint_batch(pb, y0, g, w, 0.0, 5e-9, 1e-8, 1e-12)
+    assert np.all(status == 0)
+    for i in (0, 2):
+        y1s, _, _, hs = orc.rkck_solve_rec(pb, g[:, i], y0[:, i], 0.0, 5e-9, 1e-8, 1e-12)
+        d0, dl = orc.rkck_replay_adjoint(pb, g[:, i], y0[:, i], 0.0, hs, w[:, i])
+        assert np.array_equal(y1s, y1[:, i])
+        assert np.array_equal(d0, dy0[:, i]) and np.array_equal(dl, dth[:, i])
