@@ -70,9 +70,10 @@ def cpu_baseline(w, net, y0, g, target_s: float):
 
 
 def adjoint_bench(args, w, net):
-    """One step = the taped RKC forward and the reverse sweep of the discrete
-    adjoint (checkpoint every 16 accepted steps) for L = sum w . y(t1): the
-    gradient of every system's loss with respect to y0 and ln A."""
+    """One step = the taped forward (RKC, or RKCK for the _rkck workload) and
+    the reverse sweep of the discrete adjoint (checkpoint every 16 accepted
+    steps) for L = sum w . y(t1): the gradient of every system's loss with
+    respect to y0 and ln A."""
     import numpy as np
     import torch
 
@@ -87,9 +88,11 @@ def adjoint_bench(args, w, net):
     torch.cuda.set_device(dev)
     prob = rk.Problem.network(net)
     yd, gd, wd = (torch.from_numpy(a).to(dev) for a in (y0, g, wt))
-    K, cap = 16, 4096
-    y1, st, stats, tape = rk.integrate_rkc_taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol,
-                                                 max_accepted=cap, ckpt_every=K)
+    ck = w.method == "rkck"
+    K, cap = 16, (1024 if ck else 4096)
+    taped = rk.integrate_rkck_taped if ck else rk.integrate_rkc_taped
+    y1, st, stats, tape = taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, max_accepted=cap,
+                                ckpt_every=K)
     torch.cuda.synchronize()
     if int(tape.count.min()) < 0:
         raise RuntimeError("tape too short for this workload")
@@ -99,11 +102,12 @@ def adjoint_bench(args, w, net):
     def step(ev=None):
         if ev:
             ev[0].record(stream)
-        rk.integrate_rkc_taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, max_accepted=cap,
-                               ckpt_every=K, out=y1, status=st, stats=stats)
+        taped(prob, yd, gd, w.t0, w.t1, w.rtol, w.atol, max_accepted=cap, ckpt_every=K, out=y1,
+              status=st, stats=stats)
         if ev:
             ev[1].record(stream)
-        out = rk.adjoint_rkc(prob, gd, tape, wd, max_stages=ms)
+        out = (rk.adjoint_rkck(prob, gd, tape, wd) if ck
+               else rk.adjoint_rkc(prob, gd, tape, wd, max_stages=ms))
         if ev:
             ev[2].record(stream)
         return out
@@ -130,8 +134,9 @@ def adjoint_bench(args, w, net):
     mask = torch.arange(cap, device=dev)[:, None] < cnt[None, :]
     n_steps = float(cnt.sum())
     stage_sum = float((s_tab.to(torch.int64) * mask).sum())
-    fwd_flops = FL.total("rkc", st_h, prob.n_eq, net)
-    rev_flops = FL.adjoint_reverse(prob.n_eq, net, n_steps, stage_sum)
+    fwd_flops = FL.total(w.method, st_h, prob.n_eq, net)
+    rev_flops = (FL.adjoint_reverse_rkck(prob.n_eq, net, n_steps) if ck
+                 else FL.adjoint_reverse(prob.n_eq, net, n_steps, stage_sum))
     dom_ms, dom_flops, dom = ((rev_ms, rev_flops, "adjoint_kernel") if rev_ms >= fwd_ms
                               else (fwd_ms, fwd_flops, "taped_kernel"))
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
@@ -141,7 +146,8 @@ def adjoint_bench(args, w, net):
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "method": "rkc discrete adjoint", "problem": w.problem,
+        "config": {"workload": w.name, "method": f"{w.method} discrete adjoint",
+                   "problem": w.problem,
                    "n_systems": w.n, "t0": w.t0, "t1": w.t1, "rtol": w.rtol, "atol": w.atol,
                    "ckpt_every": K, "gradients": "dL/dy0 [13] and dL/dlnA [27] per system",
                    "systems_ok": int((ast.cpu().numpy() == 0).sum()),
@@ -163,7 +169,8 @@ def adjoint_bench(args, w, net):
             idx = np.unique(np.linspace(0, w.n - 1, m).astype(np.int64))
             a = [np.ascontiguousarray(x[:, idx]) for x in (y0, g, wt)]
             t = time.perf_counter()
-            orc.rkc_adjoint_batch(pb, a[0], a[1], a[2], w.t0, w.t1, w.rtol, w.atol)
+            (orc.rkck_adjoint_batch if ck else orc.rkc_adjoint_batch)(
+                pb, a[0], a[1], a[2], w.t0, w.t1, w.rtol, w.atol)
             return len(idx), time.perf_counter() - t
 
         m, dt = run(min(w.n, max(64, 8 * cores)))
@@ -326,7 +333,7 @@ def main():
         import dataclasses
         w = dataclasses.replace(w, n=args.n)
     net = None if w.problem == "vdp" else I.network_of(w.problem)
-    if w.name.endswith("_adjoint"):
+    if "_adjoint" in w.name:
         adjoint_bench(args, w, net)
         return
     log(f"bench: workload {w.name} n={w.n}; generating inputs")

@@ -191,19 +191,20 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
                      const rk_options *opt, void *stream);
 
 /* ---------------------------------------------------------------------------
- * Discrete adjoint of RKC (Sec. 2.2 stage recursion, transposed).
+ * Discrete adjoints of RKC (Sec. 2.2 stage recursion, transposed) and of RKCK
+ * (Sec. 2.1 stage equations with the Table 1 coefficients, transposed).
  *
  * The gradient is that of the map y(t0), theta -> y(t1) through the accepted
- * steps, with every step size h_k and stage count s_k held at the values the
- * controller chose; the controller, the spectral-radius estimates and the
- * rejected attempts are not differentiated.  theta: the ln A_j of a
+ * steps, with every step size h_k (and, for RKC, stage count s_k) held at the
+ * values the controller chose; the controller, the spectral-radius estimates
+ * and the rejected attempts are not differentiated.  theta: the ln A_j of a
  * mass-action network (both rate constants of reaction j scale with A_j), or
  * mu for van der Pol.  Available for systems of up to 16 unknowns
  * (RK_EUNSUPPORTED otherwise).
  *
  * A forward call records a tape (device memory the caller allocates): per
- * system the accepted-step count, each accepted step's (h, s), and the state
- * every ckpt_every accepted steps.  Layout, for n = n_sys, C = max_accepted,
+ * system the accepted-step count, each accepted step's (h, s) (s = 6 for
+ * RKCK), and the state every ckpt_every accepted steps.  Layout, for n = n_sys, C = max_accepted,
  * K = ckpt_every:
  *   int32 count[n]          (-1: more than C accepted steps; no gradient)
  *   double h[C][n], int32 s[C][n], double y[C / K + 1][N][n]
@@ -227,6 +228,14 @@ int rk_integrate_rkc_taped(rk_problem p, int64_t n_sys, const double *y0, double
                            int64_t max_accepted, int32_t ckpt_every, const rk_options *opt,
                            void *stream);
 
+/* RKCK integration as rk_integrate_rkck (one lane per system), recording the
+ * tape as rk_integrate_rkc_taped does. */
+int rk_integrate_rkck_taped(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                            const double *g, double t0, double t1, double rtol, double atol,
+                            int32_t *status, int32_t *stats, void *tape, size_t tape_bytes,
+                            int64_t max_accepted, int32_t ckpt_every, const rk_options *opt,
+                            void *stream);
+
 /* Workspace bytes of rk_adjoint_rkc: per system max_stages stage records of
  * N + 4 doubles and ckpt_every states (0 on bad arguments).  max_stages bounds
  * the recorded stage counts (RK_STAT_MAX_STAGES of the forward call). */
@@ -247,6 +256,19 @@ int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double *g, const void *tap
                    int32_t max_stages, const double *dL_dy1, double *dL_dy0,
                    double *dL_dtheta, int32_t *status, void *ws, size_t ws_bytes,
                    void *stream);
+
+/* Workspace bytes of rk_adjoint_rkck: per system 12 N doubles (the six stage
+ * arguments and their adjoint stage increments) and ckpt_every states (0 on
+ * bad arguments). */
+size_t rk_adjoint_rkck_workspace_bytes(rk_problem p, int64_t n_sys, int32_t ckpt_every);
+
+/* Reverse sweep over a tape from rk_integrate_rkck_taped; arguments as for
+ * rk_adjoint_rkc (no stage bound), ws of at least
+ * rk_adjoint_rkck_workspace_bytes(...) bytes. */
+int rk_adjoint_rkck(rk_problem p, int64_t n_sys, const double *g, const void *tape,
+                    size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
+                    const double *dL_dy1, double *dL_dy0, double *dL_dtheta, int32_t *status,
+                    void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Ragged batches: the systems of several compiled networks of different sizes

@@ -145,13 +145,15 @@ def integrate_rkc(problem, y0, g, t0, t1, rtol, atol, **kw):
 
 
 class Tape:
-    """Device tape of an RKC integration (accepted steps' h and s, and the state
-    every ckpt_every accepted steps) for the discrete adjoint."""
+    """Device tape of an RKC or RKCK integration (accepted steps' h and s -- s = 6
+    for RKCK -- and the state every ckpt_every accepted steps) for the discrete
+    adjoint."""
 
-    def __init__(self, buf, n, max_accepted, ckpt_every, stats):
+    def __init__(self, buf, n, max_accepted, ckpt_every, stats, method=RK_METHOD_RKC):
         self.buf, self.n = buf, n
         self.max_accepted, self.ckpt_every = max_accepted, ckpt_every
         self.stats = stats
+        self.method = method
 
     def _offsets(self):
         def a256(x):
@@ -185,9 +187,23 @@ class Tape:
 
 
 def integrate_rkc_taped(problem, y0, g, t0, t1, rtol, atol, max_accepted=4096, ckpt_every=16,
-                        out=None, status=None, stats=None, stream=None, **opts):
+                        **kw):
     """RKC integration that also records the tape of the discrete adjoint.
     Returns (y1, status, stats, tape)."""
+    return _integrate_taped(RK_METHOD_RKC, problem, y0, g, t0, t1, rtol, atol, max_accepted,
+                            ckpt_every, **kw)
+
+
+def integrate_rkck_taped(problem, y0, g, t0, t1, rtol, atol, max_accepted=4096, ckpt_every=16,
+                         **kw):
+    """RKCK integration that also records the tape of the discrete adjoint.
+    Returns (y1, status, stats, tape)."""
+    return _integrate_taped(RK_METHOD_RKCK, problem, y0, g, t0, t1, rtol, atol, max_accepted,
+                            ckpt_every, **kw)
+
+
+def _integrate_taped(method, problem, y0, g, t0, t1, rtol, atol, max_accepted, ckpt_every,
+                     out=None, status=None, stats=None, stream=None, **opts):
     import torch
     if y0.dim() != 2:
         raise ValueError("y0 must be [N, n]")
@@ -209,12 +225,13 @@ def integrate_rkc_taped(problem, y0, g, t0, t1, rtol, atol, max_accepted=4096, c
     with torch.cuda.device(dev):
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         buf = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
-        _lib.check(L.rk_integrate_rkc_taped(
+        fn = L.rk_integrate_rkck_taped if method == RK_METHOD_RKCK else L.rk_integrate_rkc_taped
+        _lib.check(fn(
             problem.handle, n, y0.data_ptr(), out.data_ptr(),
             g.data_ptr() if problem.n_param else None, float(t0), float(t1), float(rtol),
             float(atol), status.data_ptr(), stats.data_ptr(), buf.data_ptr(), nb,
             int(max_accepted), int(ckpt_every), optp, s.cuda_stream))
-    return out, status, stats, Tape(buf, n, int(max_accepted), int(ckpt_every), stats)
+    return out, status, stats, Tape(buf, n, int(max_accepted), int(ckpt_every), stats, method)
 
 
 def adjoint_rkc(problem, g, tape, dL_dy1, max_stages=None, stream=None):
@@ -242,19 +259,46 @@ def adjoint_rkc(problem, g, tape, dL_dy1, max_stages=None, stream=None):
     return dy0, dth[:problem.n_theta], st
 
 
-def _autograd_function():
+def adjoint_rkck(problem, g, tape, dL_dy1, stream=None):
+    """Reverse sweep of the discrete RKCK adjoint over `tape` (from
+    integrate_rkck_taped).  Returns (dL/dy0 [N, n], per-system dL/dtheta
+    [n_theta, n], status [n])."""
     import torch
+    n = tape.n
+    _check_tensor(dL_dy1, "dL_dy1", problem.n_eq, n, torch.float64)
+    dev = dL_dy1.device
+    L = _lib.lib()
+    dy0 = torch.empty_like(dL_dy1)
+    dth = torch.empty((max(problem.n_theta, 1), n), dtype=torch.float64, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+    nws = L.rk_adjoint_rkck_workspace_bytes(problem.handle, n, tape.ckpt_every)
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+        _lib.check(L.rk_adjoint_rkck(problem.handle, n,
+                                     g.data_ptr() if problem.n_param else None,
+                                     tape.buf.data_ptr(), tape.buf.numel(), tape.max_accepted,
+                                     tape.ckpt_every, dL_dy1.data_ptr(), dy0.data_ptr(),
+                                     dth.data_ptr(), st.data_ptr(), ws.data_ptr(), nws,
+                                     s.cuda_stream))
+    return dy0, dth[:problem.n_theta], st
 
-    class RKCAdjoint(torch.autograd.Function):
-        """y1 = RKC(y0; theta) with the discrete adjoint as its backward.
-        Inputs: y0 [N, n]; g [P, n] (for van der Pol its row 0, mu, is the
-        differentiable parameter); lnA [n_rx] or None (networks: the shared
-        ln A_j, whose gradient sums the per-system contributions)."""
+
+def _autograd_function(method):
+    import torch
+    taped = integrate_rkck_taped if method == RK_METHOD_RKCK else integrate_rkc_taped
+    reverse = adjoint_rkck if method == RK_METHOD_RKCK else adjoint_rkc
+
+    class Adjoint(torch.autograd.Function):
+        """y1 = RKC(y0; theta) or RKCK(y0; theta) with the discrete adjoint as its
+        backward.  Inputs: y0 [N, n]; g [P, n] (for van der Pol its row 0, mu,
+        is the differentiable parameter); lnA [n_rx] or None (networks: the
+        shared ln A_j, whose gradient sums the per-system contributions)."""
 
         @staticmethod
         def forward(ctx, y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted, ckpt_every):
             while True:
-                y1, status, stats, tape = integrate_rkc_taped(
+                y1, status, stats, tape = taped(
                     problem, y0.detach(), g.detach() if g is not None else None, t0, t1, rtol,
                     atol, max_accepted=max_accepted, ckpt_every=ckpt_every)
                 if int(tape.count.min().item()) >= 0 or y0.shape[1] == 0:
@@ -268,7 +312,7 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, gy1, _gst, _gstats):
             (g,) = ctx.saved_tensors
-            dy0, dth, st = adjoint_rkc(ctx.problem, g, ctx.tape, gy1.contiguous())
+            dy0, dth, st = reverse(ctx.problem, g, ctx.tape, gy1.contiguous())
             dg = dlnA = None
             if ctx.problem.kind == "vdp" and ctx.needs_input_grad[1]:
                 dg = dth
@@ -276,10 +320,11 @@ def _autograd_function():
                 dlnA = dth.sum(1)
             return dy0, dg, dlnA, None, None, None, None, None, None, None
 
-    return RKCAdjoint
+    Adjoint.__name__ = "RKCKAdjoint" if method == RK_METHOD_RKCK else "RKCAdjoint"
+    return Adjoint
 
 
-_RKCAdjoint = None
+_adjoint_fns = {}
 _lnA_problems = {}
 
 
@@ -288,9 +333,19 @@ def rkc_solve(problem, y0, g, t0, t1, rtol, atol, lnA=None, max_accepted=4096, c
     autograd graph of y0, g (van der Pol: mu) and lnA (networks, [n_rx]; the
     problem's own values when None).  The backward pass is the discrete
     adjoint, checkpointed every ckpt_every accepted steps."""
-    global _RKCAdjoint
-    if _RKCAdjoint is None:
-        _RKCAdjoint = _autograd_function()
+    return _solve(RK_METHOD_RKC, problem, y0, g, t0, t1, rtol, atol, lnA, max_accepted,
+                  ckpt_every)
+
+
+def rkck_solve(problem, y0, g, t0, t1, rtol, atol, lnA=None, max_accepted=4096, ckpt_every=16):
+    """Differentiable RKCK integration, as rkc_solve."""
+    return _solve(RK_METHOD_RKCK, problem, y0, g, t0, t1, rtol, atol, lnA, max_accepted,
+                  ckpt_every)
+
+
+def _solve(method, problem, y0, g, t0, t1, rtol, atol, lnA, max_accepted, ckpt_every):
+    if method not in _adjoint_fns:
+        _adjoint_fns[method] = _autograd_function(method)
     if lnA is not None:
         import dataclasses
 
@@ -306,7 +361,8 @@ def rkc_solve(problem, y0, g, t0, t1, rtol, atol, lnA=None, max_accepted=4096, c
                 _lnA_problems.clear()
                 _lnA_problems[key] = Problem.network(dataclasses.replace(problem.net, lnA=vals))
             problem = _lnA_problems[key]
-    return _RKCAdjoint.apply(y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted, ckpt_every)
+    return _adjoint_fns[method].apply(y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted,
+                                      ckpt_every)
 
 
 class Batch:

@@ -82,6 +82,13 @@ def lib():
                                              C.c_double, C.c_double, vp, vp, vp, C.c_size_t,
                                              i64, C.c_int32, C.POINTER(Options), vp]
         L.rk_integrate_rkc_taped.restype = C.c_int
+        L.rk_integrate_rkck_taped.argtypes = L.rk_integrate_rkc_taped.argtypes
+        L.rk_integrate_rkck_taped.restype = C.c_int
+        L.rk_adjoint_rkck_workspace_bytes.argtypes = [vp, i64, C.c_int32]
+        L.rk_adjoint_rkck_workspace_bytes.restype = C.c_size_t
+        L.rk_adjoint_rkck.argtypes = [vp, i64, dp, vp, C.c_size_t, i64, C.c_int32, dp, dp, dp,
+                                      vp, vp, C.c_size_t, vp]
+        L.rk_adjoint_rkck.restype = C.c_int
         L.rk_adjoint_workspace_bytes.argtypes = [vp, i64, C.c_int32, C.c_int32]
         L.rk_adjoint_workspace_bytes.restype = C.c_size_t
         L.rk_adjoint_rkc.argtypes = [vp, i64, dp, vp, C.c_size_t, i64, C.c_int32, C.c_int32, dp,

@@ -401,27 +401,46 @@ int rk_integrate_rkc_taped(rk_problem p, int64_t n_sys, const double* y0, double
                    nullptr, 0, opt, stream, &t);
 }
 
-size_t rk_adjoint_workspace_bytes(rk_problem p, int64_t n_sys, int32_t max_stages,
-                                  int32_t ckpt_every) {
-  g_err.clear();
-  if (!p || n_sys <= 0 || max_stages < 2 || ckpt_every < 1) return 0;
+int rk_integrate_rkck_taped(rk_problem p, int64_t n_sys, const double* y0, double* y1,
+                            const double* g, double t0, double t1, double rtol, double atol,
+                            int32_t* status, int32_t* stats, void* tape, size_t tape_bytes,
+                            int64_t max_accepted, int32_t ckpt_every, const rk_options* opt,
+                            void* stream) {
+  const rkmi::TapeArgs t{tape, tape_bytes, max_accepted, ckpt_every};
+  return integrate(rkmi::kMethodRkck, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats,
+                   nullptr, 0, opt, stream, &t);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Adjoint workspace: per 64 systems one block of per-lane columns (RKC:
+// max_stages stage records of N + 4 doubles; RKCK: 12 N doubles), plus
+// ckpt_every step-start states.
+size_t adjoint_ws_bytes(int method, rk_problem p, int64_t n_sys, int32_t max_stages,
+                        int32_t ckpt_every) {
+  if (!p || n_sys <= 0 || ckpt_every < 1) return 0;
+  if (method == rkmi::kMethodRkc && max_stages < 2) return 0;
   const int64_t blocks = (n_sys + rkmi::kLdsStride - 1) / rkmi::kLdsStride;
-  const int64_t rows = (int64_t)max_stages * (p->n_eq + 4) + (int64_t)ckpt_every * p->n_eq;
+  const int64_t per = method == rkmi::kMethodRkck ? 12 * (int64_t)p->n_eq
+                                                  : (int64_t)max_stages * (p->n_eq + 4);
+  const int64_t rows = per + (int64_t)ckpt_every * p->n_eq;
   return (size_t)(blocks * rows * rkmi::kLdsStride * (int64_t)sizeof(double));
 }
 
-int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double* g, const void* tape,
-                   size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
-                   int32_t max_stages, const double* dL_dy1, double* dL_dy0, double* dL_dtheta,
-                   int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+int adjoint(int method, rk_problem p, int64_t n_sys, const double* g, const void* tape,
+            size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every, int32_t max_stages,
+            const double* dL_dy1, double* dL_dy0, double* dL_dtheta, int32_t* status, void* ws,
+            size_t ws_bytes, void* stream) {
   g_err.clear();
   if (!p) return fail(RK_EINVAL, "problem handle is NULL");
   if (!p->adjoint)
     return fail(RK_EUNSUPPORTED, "the adjoint is not compiled for this problem (systems of "
                 "more than 16 unknowns keep their vectors in workspace columns)");
   if (n_sys < 0) return fail(RK_EINVAL, "n_sys = %lld is negative", (long long)n_sys);
-  if (ckpt_every < 1 || max_accepted < 0 || max_stages < 2)
-    return fail(RK_EINVAL, "need ckpt_every >= 1, max_accepted >= 0 and max_stages >= 2");
+  if (ckpt_every < 1 || max_accepted < 0 || (method == rkmi::kMethodRkc && max_stages < 2))
+    return fail(RK_EINVAL, "need ckpt_every >= 1, max_accepted >= 0 and (RKC) max_stages >= 2");
   if (n_sys == 0) return RK_OK;
   int rc;
   if ((rc = check_device_ptr(g, 8, "g", p->n_param == 0))) return rc;
@@ -434,10 +453,11 @@ int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double* g, const void* tap
   const size_t tneed = rkmi::tape_layout(n_sys, max_accepted, ckpt_every, p->n_eq).bytes;
   if (tape_bytes < tneed)
     return fail(RK_EINVAL, "tape of %zu bytes is smaller than its layout (%zu)", tape_bytes, tneed);
-  const size_t wneed = rk_adjoint_workspace_bytes(p, n_sys, max_stages, ckpt_every);
+  const size_t wneed = adjoint_ws_bytes(method, p, n_sys, max_stages, ckpt_every);
   if (ws_bytes < wneed)
     return fail(RK_EWORKSPACE, "workspace of %zu bytes is too small (%zu needed)", ws_bytes, wneed);
   rkmi::AdjointArgs a{};
+  a.method = method;
   a.n = n_sys;
   a.g = g;
   a.tape = rkmi::TapeArgs{const_cast<void*>(tape), tape_bytes, max_accepted, ckpt_every};
@@ -452,6 +472,37 @@ int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double* g, const void* tap
   rc = p->adjoint(&a, stream);
   if (rc) return fail(RK_EHIP, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
   return RK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rk_adjoint_workspace_bytes(rk_problem p, int64_t n_sys, int32_t max_stages,
+                                  int32_t ckpt_every) {
+  g_err.clear();
+  return adjoint_ws_bytes(rkmi::kMethodRkc, p, n_sys, max_stages, ckpt_every);
+}
+
+size_t rk_adjoint_rkck_workspace_bytes(rk_problem p, int64_t n_sys, int32_t ckpt_every) {
+  g_err.clear();
+  return adjoint_ws_bytes(rkmi::kMethodRkck, p, n_sys, 0, ckpt_every);
+}
+
+int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double* g, const void* tape,
+                   size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
+                   int32_t max_stages, const double* dL_dy1, double* dL_dy0, double* dL_dtheta,
+                   int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  return adjoint(rkmi::kMethodRkc, p, n_sys, g, tape, tape_bytes, max_accepted, ckpt_every,
+                 max_stages, dL_dy1, dL_dy0, dL_dtheta, status, ws, ws_bytes, stream);
+}
+
+int rk_adjoint_rkck(rk_problem p, int64_t n_sys, const double* g, const void* tape,
+                    size_t tape_bytes, int64_t max_accepted, int32_t ckpt_every,
+                    const double* dL_dy1, double* dL_dy0, double* dL_dtheta, int32_t* status,
+                    void* ws, size_t ws_bytes, void* stream) {
+  return adjoint(rkmi::kMethodRkck, p, n_sys, g, tape, tape_bytes, max_accepted, ckpt_every, 0,
+                 dL_dy1, dL_dy0, dL_dtheta, status, ws, ws_bytes, stream);
 }
 
 struct rk_batch_s {
@@ -664,27 +715,32 @@ int rkmi_test_host_integrate(int32_t method, rk_problem p, int64_t n, const doub
 
 // Test hooks, not part of the public ABI: the taped forward and the adjoint's
 // per-system code run on the host over HOST arrays (tape and workspace too).
-int rkmi_test_host_taped(rk_problem p, int64_t n, const double* y0, double* y1, const double* g,
-                         double t0, double t1, double rtol, double atol, int32_t* status,
-                         int32_t* stats, void* tape, size_t tape_bytes, int64_t cap, int32_t K) {
+int rkmi_test_host_taped(rk_problem p, int32_t method, int64_t n, const double* y0, double* y1,
+                         const double* g, double t0, double t1, double rtol, double atol,
+                         int32_t* status, int32_t* stats, void* tape, size_t tape_bytes,
+                         int64_t cap, int32_t K) {
   g_err.clear();
   if (!p || !p->taped_host || n < 0 || !y0 || !y1 || (p->n_param && !g) || !(t1 >= t0) ||
-      !(rtol > 0.0) || !(atol >= 0.0) || !tape || K < 1 || cap < 0)
+      !(rtol > 0.0) || !(atol >= 0.0) || !tape || K < 1 || cap < 0 ||
+      (method != RK_METHOD_RKCK && method != RK_METHOD_RKC))
     return fail(RK_EINVAL, "invalid arguments");
   rkmi::LaunchArgs a;
-  fill_args(a, rkmi::kMethodRkc, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0,
-            nullptr);
+  fill_args(a, method == RK_METHOD_RKCK ? rkmi::kMethodRkck : rkmi::kMethodRkc, n, y0, y1, g, t0,
+            t1, rtol, atol, status, stats, nullptr, 0, nullptr);
   a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
   const rkmi::TapeArgs t{tape, tape_bytes, cap, K};
   return p->taped_host(&a, &t);
 }
 
-int rkmi_test_host_adjoint(rk_problem p, int64_t n, const double* g, void* tape,
+int rkmi_test_host_adjoint(rk_problem p, int32_t method, int64_t n, const double* g, void* tape,
                            size_t tape_bytes, int64_t cap, int32_t K, int32_t max_stages,
                            const double* w, double* dy0, double* dth, int32_t* status) {
   g_err.clear();
-  if (!p || !p->adjoint_host || n < 0 || !tape || !w || !dy0) return fail(RK_EINVAL, "invalid arguments");
+  if (!p || !p->adjoint_host || n < 0 || !tape || !w || !dy0 ||
+      (method != RK_METHOD_RKCK && method != RK_METHOD_RKC))
+    return fail(RK_EINVAL, "invalid arguments");
   rkmi::AdjointArgs a{};
+  a.method = method == RK_METHOD_RKCK ? rkmi::kMethodRkck : rkmi::kMethodRkc;
   a.n = n;
   a.g = g;
   a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();

@@ -1,4 +1,4 @@
-// rk_adjoint.hpp -- discrete adjoint of the RKC step sequence.
+// rk_adjoint.hpp -- discrete adjoints of the RKC and RKCK step sequences.
 //
 // The gradient is that of the map from y(t0) (and the problem's parameters
 // theta) to y(t1) through the accepted steps, with each step's size h_k and
@@ -18,6 +18,15 @@
 // recomputed from the segment's checkpoint; per step, last first, the stages
 // w_0..w_{s-1} and their coefficients are recomputed into the lane's columns
 // and the transposed recursion runs in registers.  One lane per system.
+//
+// RKCK (Sec. 2.1 stage equations with the Table 1 coefficients), step sizes
+// held fixed: with z_1 = y, z_i = y + sum_{j<i} b_ij k_j, k_i = h f(z_i) and
+// y' = y + sum_i c_i k_i, the transpose for lambda = dL/dy' is
+//   kbar_i = c_i lambda,  ybar = lambda;  for i = 6..1:
+//     u = h kbar_i,  zbar = J(z_i)^T u,  theta^ += (df/dtheta)(z_i)^T u,
+//     ybar += zbar,  kbar_j += b_ij zbar (j < i);
+// ybar is lambda for the step before.  The reverse sweep recomputes a step's
+// stage arguments z_i into the lane's columns, next to the kbar_i.
 #pragma once
 
 #include "rk_launch.hpp"
@@ -109,27 +118,42 @@ struct StageRecorder {
   }
 };
 
-// Rows of a lane's adjoint columns: max_stages stage records, K step starts.
-template <class Prob>
+// RKCK stage arguments z_2..z_6 of one step into rows (i - 1) N .. of the
+// lane's columns (z_1 = y is stored by the caller).
+template <int N>
+struct RkckStageRecorder {
+  double* col;
+  template <class V>
+  RKMI_HD void rkck_stage(int i, const V& z) {
+    double* r = col + (int64_t)(i - 1) * N * kLdsStride;
+#pragma unroll
+    for (int k = 0; k < N; ++k) r[k * kLdsStride] = z[k];
+  }
+};
+
+// Rows of a lane's adjoint columns.  RKC: max_stages stage records, K step
+// starts.  RKCK: six stage arguments z_i, six kbar_i, K step starts.
+template <class Prob, int Method>
 RKMI_HD int64_t adjoint_rows(int max_stages, int K) {
+  if (Method == kMethodRkck) return (int64_t)12 * Prob::N + (int64_t)K * Prob::N;
   return (int64_t)max_stages * (Prob::N + 4) + (int64_t)K * Prob::N;
 }
 
-// Forward integration of system i with its tape.
-template <class Prob>
+// Forward integration of system i with its tape (RKCK records s = 6).
+template <class Prob, int Method>
 RKMI_HD void taped_system(const typename Prob::Params& prm, int64_t n, int64_t i,
                           const double* y0, double* y1, const double* g, const Ctl& c,
                           int32_t* status, int32_t* stats, const TapeView& T, double* slot) {
   TapeRec<Prob::N> R{T, i, false};
-  Driver<Prob, kMethodRkc, TapeRec<Prob::N>> D;
+  Driver<Prob, Method, TapeRec<Prob::N>> D;
   D.rec = &R;
   const bool go = D.start(prm, c, n, i, y0, g, slot);
-  R.checkpoint(0, D.S.yn);
+  R.checkpoint(0, D.state());
   if (go)
     while (D.attempt(prm, c, slot)) {
     }
   D.finish(n, i, y1, status, stats);
-  T.count[i] = R.full ? -1 : (int32_t)D.S.nstep;
+  T.count[i] = R.full ? -1 : (int32_t)D.accepted();
 }
 
 // Reverse sweep of system i; returns its status.  lambda = w[:, i] on entry,
@@ -254,7 +278,96 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
   return st;
 }
 
+// Reverse sweep of system i under RKCK, as adjoint_system.
 template <class Prob>
+RKMI_HD int32_t adjoint_system_rkck(const typename Prob::Params& prm, int64_t n, int64_t i,
+                                    const double* g, const TapeView& T, const double* w,
+                                    double* dy0, double* dth, double* slot, double* col) {
+  constexpr int N = Prob::N, NT = Prob::kNTheta;
+  using V = RegVec<N>;
+  typename Prob::Lane L;
+  Prob::init(L, prm, g, i, n, slot);
+  const int64_t M = T.count[i];
+  V lam;
+  double th[NT];
+#pragma unroll
+  for (int k = 0; k < N; ++k) lam[k] = w[(int64_t)k * n + i];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) th[q] = 0.0;
+  int32_t st = M < 0 ? kSysTape : kSysOk;
+  double* const zc = col;                                 // z_1..z_6
+  double* const kc = col + (int64_t)6 * N * kLdsStride;   // kbar_1..kbar_6
+  double* const ys = col + (int64_t)12 * N * kLdsStride;  // step starts of a segment
+  for (int64_t seg = M > 0 ? (M - 1) / T.K : -1; st == kSysOk && seg >= 0; --seg) {
+    const int64_t k0 = seg * T.K;
+    const int64_t k1 = (k0 + T.K < M) ? k0 + T.K : M;
+    V y;
+#pragma unroll
+    for (int r = 0; r < N; ++r) y[r] = T.ckpt[(seg * N + r) * n + i];
+    for (int64_t k = k0; k < k1; ++k) {
+      double* const yk = ys + (k - k0) * N * kLdsStride;
+#pragma unroll
+      for (int r = 0; r < N; ++r) yk[r * kLdsStride] = y[r];
+      if (k + 1 < k1) {
+        V F, yt, ye;
+        Prob::rhs(L, prm, y, F);
+        rkck_trial<Prob>(L, prm, y, F, T.h[k * n + i], yt, ye, slot);
+        y = yt;
+      }
+    }
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      const double hk = T.h[k * n + i];
+      const double* const yk = ys + (k - k0) * N * kLdsStride;
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        y[r] = yk[r * kLdsStride];
+        zc[r * kLdsStride] = y[r];
+      }
+      {
+        V F, yt, ye;
+        Prob::rhs(L, prm, y, F);
+        RkckStageRecorder<N> R{zc};
+        rkck_trial<Prob, RkckStageRecorder<N>>(L, prm, y, F, hk, yt, ye, slot, &R);
+      }
+      V yb, u, jtu, z;
+      for (int s6 = 0; s6 < 6; ++s6) {
+        double* const kb = kc + (int64_t)s6 * N * kLdsStride;
+#pragma unroll
+        for (int r = 0; r < N; ++r) kb[r * kLdsStride] = ck::kC[s6] * lam[r];
+      }
+#pragma unroll
+      for (int r = 0; r < N; ++r) yb[r] = lam[r];
+      for (int si = 5; si >= 0; --si) {
+        const double* const kb = kc + (int64_t)si * N * kLdsStride;
+        const double* const zi = zc + (int64_t)si * N * kLdsStride;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+          u[r] = hk * kb[r * kLdsStride];
+          z[r] = zi[r * kLdsStride];
+        }
+        Prob::vjp(L, prm, z, u, jtu, th);
+#pragma unroll
+        for (int r = 0; r < N; ++r) yb[r] += jtu[r];
+        for (int j = 0; j < si; ++j) {
+          double* const kj = kc + (int64_t)j * N * kLdsStride;
+          const double b = ck::kB[si][j];
+#pragma unroll
+          for (int r = 0; r < N; ++r) kj[r * kLdsStride] += b * jtu[r];
+        }
+      }
+      lam = yb;
+    }
+  }
+  const double nan = crm::from_bits(0x7ff8000000000000ull);
+#pragma unroll
+  for (int k = 0; k < N; ++k) dy0[(int64_t)k * n + i] = st == kSysOk ? lam[k] : nan;
+  if (dth)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) dth[(int64_t)q * n + i] = st == kSysOk ? th[q] : nan;
+  return st;
+}
+
+template <class Prob, int Method>
 __global__ __launch_bounds__(kLdsStride)
 __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void taped_kernel(typename Prob::Params prm, int64_t n,
                                                            const double* y0, double* y1,
@@ -262,13 +375,13 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void taped_kernel(
                                                            int32_t* __restrict__ status,
                                                            int32_t* __restrict__ stats,
                                                            TapeView T) {
-  __shared__ double lds[kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride];
+  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n) return;
-  taped_system<Prob>(prm, n, i, y0, y1, g, c, status, stats, T, lds + threadIdx.x);
+  taped_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats, T, lds + threadIdx.x);
 }
 
-template <class Prob>
+template <class Prob, int Method>
 __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Params prm, int64_t n,
                                                              const double* __restrict__ g,
                                                              TapeView T, int max_stages,
@@ -277,21 +390,25 @@ __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Para
                                                              double* __restrict__ dth,
                                                              int32_t* __restrict__ status,
                                                              double* cols) {
-  __shared__ double lds[kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride];
+  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n) return;
-  double* const col =
-      cols + (int64_t)blockIdx.x * adjoint_rows<Prob>(max_stages, T.K) * kLdsStride + threadIdx.x;
-  const int32_t st =
-      adjoint_system<Prob>(prm, n, i, g, T, max_stages, w, dy0, dth, lds + threadIdx.x, col);
+  double* const col = cols +
+                      (int64_t)blockIdx.x * adjoint_rows<Prob, Method>(max_stages, T.K) * kLdsStride +
+                      threadIdx.x;
+  int32_t st;
+  if constexpr (Method == kMethodRkck)
+    st = adjoint_system_rkck<Prob>(prm, n, i, g, T, w, dy0, dth, lds + threadIdx.x, col);
+  else
+    st = adjoint_system<Prob>(prm, n, i, g, T, max_stages, w, dy0, dth, lds + threadIdx.x, col);
   if (status) status[i] = st;
 }
 
 // Bytes of adjoint workspace for n systems (one column block per 64 systems).
-template <class Prob>
+template <class Prob, int Method>
 int64_t adjoint_workspace_bytes(int64_t n, int max_stages, int K) {
   const int64_t blocks = (n + kLdsStride - 1) / kLdsStride;
-  return blocks * adjoint_rows<Prob>(max_stages, K) * kLdsStride * (int64_t)sizeof(double);
+  return blocks * adjoint_rows<Prob, Method>(max_stages, K) * kLdsStride * (int64_t)sizeof(double);
 }
 
 template <class Prob>
@@ -304,9 +421,13 @@ int launch_taped(const LaunchArgs* a, const TapeArgs* t, void* stream) {
       t->tape_bytes < tape_layout(a->n, t->cap, t->K, Prob::N).bytes)
     return kLaunchWorkspace;
   const TapeView T = tape_view(*t, a->n, Prob::N);
-  taped_kernel<Prob><<<dim3((unsigned)blocks), dim3(kLdsStride), 0,
-                       static_cast<hipStream_t>(stream)>>>(a->prm, a->n, a->y0, a->y1, a->g,
-                                                           a->ctl, a->status, a->stats, T);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (a->method == kMethodRkck)
+    taped_kernel<Prob, kMethodRkck><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T);
+  else
+    taped_kernel<Prob, kMethodRkc><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
@@ -318,14 +439,20 @@ int launch_adjoint(const AdjointArgs* a, void* stream) {
   if (!a->tape.tape || a->tape.K < 1 || a->tape.cap < 0 ||
       a->tape.tape_bytes < tape_layout(a->n, a->tape.cap, a->tape.K, Prob::N).bytes)
     return kLaunchInvalid;
-  if (a->max_stages < 2 || !a->ws ||
-      a->ws_bytes < (size_t)adjoint_workspace_bytes<Prob>(a->n, a->max_stages, a->tape.K))
-    return kLaunchWorkspace;
+  const bool ck = a->method == kMethodRkck;
+  const int64_t need = ck ? adjoint_workspace_bytes<Prob, kMethodRkck>(a->n, 0, a->tape.K)
+                          : adjoint_workspace_bytes<Prob, kMethodRkc>(a->n, a->max_stages,
+                                                                      a->tape.K);
+  if ((!ck && a->max_stages < 2) || !a->ws || a->ws_bytes < (size_t)need) return kLaunchWorkspace;
   const TapeView T = tape_view(a->tape, a->n, Prob::N);
-  adjoint_kernel<Prob><<<dim3((unsigned)blocks), dim3(kLdsStride), 0,
-                         static_cast<hipStream_t>(stream)>>>(
-      a->prm, a->n, a->g, T, a->max_stages, a->w, a->dy0, a->dth, a->status,
-      static_cast<double*>(a->ws));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ck)
+    adjoint_kernel<Prob, kMethodRkck><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        a->prm, a->n, a->g, T, 0, a->w, a->dy0, a->dth, a->status, static_cast<double*>(a->ws));
+  else
+    adjoint_kernel<Prob, kMethodRkc><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
+        a->prm, a->n, a->g, T, a->max_stages, a->w, a->dy0, a->dth, a->status,
+        static_cast<double*>(a->ws));
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
@@ -336,23 +463,34 @@ int host_taped(const LaunchArgs* a, const TapeArgs* t) {
     return kLaunchWorkspace;
   const TapeView T = tape_view(*t, a->n, Prob::N);
   std::vector<double> slot((size_t)kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride);
-  for (int64_t i = 0; i < a->n; ++i)
-    taped_system<Prob>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T,
-                       slot.data());
+  for (int64_t i = 0; i < a->n; ++i) {
+    if (a->method == kMethodRkck)
+      taped_system<Prob, kMethodRkck>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
+                                      a->stats, T, slot.data());
+    else
+      taped_system<Prob, kMethodRkc>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
+                                     a->stats, T, slot.data());
+  }
   return kLaunchOk;
 }
 
 template <class Prob>
 int host_adjoint(const AdjointArgs* a) {
-  if (!a->tape.tape || a->tape.K < 1 || a->max_stages < 2 ||
+  const bool ck = a->method == kMethodRkck;
+  if (!a->tape.tape || a->tape.K < 1 || (!ck && a->max_stages < 2) ||
       a->tape.tape_bytes < tape_layout(a->n, a->tape.cap, a->tape.K, Prob::N).bytes)
     return kLaunchInvalid;
   const TapeView T = tape_view(a->tape, a->n, Prob::N);
   std::vector<double> slot((size_t)kernel_lds_doubles<Prob, kMethodRkc>() * kLdsStride);
-  std::vector<double> col((size_t)adjoint_rows<Prob>(a->max_stages, a->tape.K) * kLdsStride);
+  const int64_t rows = ck ? adjoint_rows<Prob, kMethodRkck>(0, a->tape.K)
+                          : adjoint_rows<Prob, kMethodRkc>(a->max_stages, a->tape.K);
+  std::vector<double> col((size_t)rows * kLdsStride);
   for (int64_t i = 0; i < a->n; ++i) {
-    const int32_t st = adjoint_system<Prob>(a->prm, a->n, i, a->g, T, a->max_stages, a->w,
-                                            a->dy0, a->dth, slot.data(), col.data());
+    const int32_t st =
+        ck ? adjoint_system_rkck<Prob>(a->prm, a->n, i, a->g, T, a->w, a->dy0, a->dth,
+                                       slot.data(), col.data())
+           : adjoint_system<Prob>(a->prm, a->n, i, a->g, T, a->max_stages, a->w, a->dy0,
+                                  a->dth, slot.data(), col.data());
     if (a->status) a->status[i] = st;
   }
   return kLaunchOk;

@@ -205,14 +205,44 @@ constexpr double c1 = 37.0 / 378.0, c3 = 250.0 / 621.0, c4 = 125.0 / 594.0, c6 =
 // c_i - c*_i, exact rational differences rounded once
 constexpr double e1 = -277.0 / 64512.0, e3 = 6925.0 / 370944.0, e4 = -6925.0 / 202752.0,
                  e5 = -277.0 / 14336.0, e6 = 277.0 / 7084.0;
+// the stage couplings and weights as tables (row i: stage i + 1), zero where
+// Table 1 has no entry
+constexpr double kB[6][5] = {{0.0, 0.0, 0.0, 0.0, 0.0},
+                             {b21, 0.0, 0.0, 0.0, 0.0},
+                             {b31, b32, 0.0, 0.0, 0.0},
+                             {b41, b42, b43, 0.0, 0.0},
+                             {b51, b52, b53, b54, 0.0},
+                             {b61, b62, b63, b64, b65}};
+constexpr double kC[6] = {c1, 0.0, c3, c4, 0.0, c6};
 }  // namespace ck
+
+// Observer of the stages of a step (the adjoint records them).  RKC: first()
+// sees w_0 and mut_1, stage(j, ...) sees w_{j-1} with the coefficients of
+// stage j before f(w_{j-1}) is formed; with kStopAtLast the step ends after
+// stage(s, ...), without forming w_s.  RKCK: rkck_stage(i, z) sees the
+// argument z_i of stage i = 2..6 before f(z_i) is formed.
+struct NoSink {
+  static constexpr bool kStopAtLast = false;
+  template <class V>
+  RKMI_HD void first(const V&, double) {}
+  template <class V>
+  RKMI_HD void stage(int, const V&, double, double, double, double) {}
+  template <class V>
+  RKMI_HD void rkck_stage(int, const V&) {}
+};
+
+// Observer of accepted steps (the adjoint's forward tape).
+struct NoRec {
+  template <class V>
+  RKMI_HD void accept(double, int, const V&, int64_t) {}
+};
 
 // One trial step: k_1 = h F, k_i = h f(y + sum_j b_ij k_j); returns the
 // fifth-order solution and the error estimate sum_i (c_i - c*_i) k_i.
-template <class Prob>
+template <class Prob, class Sink = NoSink>
 RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Params& prm,
                         const Vec<Prob>& y, const Vec<Prob>& F, double h, Vec<Prob>& yt,
-                        Vec<Prob>& ye, double* slot) {
+                        Vec<Prob>& ye, double* slot, Sink* sink = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
   Vec<Prob> k1 = work_vec<Prob>(slot, kCkK1), k2 = work_vec<Prob>(slot, kCkK2),
             k3 = work_vec<Prob>(slot, kCkK3), k4 = work_vec<Prob>(slot, kCkK4),
@@ -223,24 +253,28 @@ RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Param
     k1[i] = h * F[i];
     z[i] = y[i] + ck::b21 * k1[i];
   }
+  if (sink) sink->rkck_stage(2, z);
   eval_rhs<Prob>(L, prm, z, f);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
     k2[i] = h * f[i];
     z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
   }
+  if (sink) sink->rkck_stage(3, z);
   eval_rhs<Prob>(L, prm, z, f);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
     k3[i] = h * f[i];
     z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
   }
+  if (sink) sink->rkck_stage(4, z);
   eval_rhs<Prob>(L, prm, z, f);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
     k4[i] = h * f[i];
     z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
   }
+  if (sink) sink->rkck_stage(5, z);
   eval_rhs<Prob>(L, prm, z, f);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
@@ -248,6 +282,7 @@ RKMI_HD void rkck_trial(const typename Prob::Lane& L, const typename Prob::Param
     z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
            ck::b65 * k5[i];
   }
+  if (sink) sink->rkck_stage(6, z);
   eval_rhs<Prob>(L, prm, z, f);
 #pragma unroll U
   for (int i = 0; i < N; ++i) {
@@ -291,9 +326,9 @@ RKMI_HD void rkck_begin(RkckState<Prob>& S, const Ctl& c) {
 
 // One attempted step of the RKCK driver (Sec. 3.1); returns true while the
 // system still has to step (t < t1 and no failure).
-template <class Prob>
+template <class Prob, class Rec = NoRec>
 RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
-                          const Ctl& c, RkckState<Prob>& S, double* slot) {
+                          const Ctl& c, RkckState<Prob>& S, double* slot, Rec* rec = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
   if (S.attempts >= c.max_steps) {
     S.status = kSysMaxSteps;
@@ -330,10 +365,12 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
     }
   } else {
     S.t += S.h;
+    const double hacc = S.h;
     const double hn = (err > kErrCon) ? kSafety * S.h * crm::cr_pow(err, kPGrow) : S.h * 5.0;
     S.h = fmax(kRkckHmin, fmin(c.hmax, hn));
     copy<Prob>(S.y, yt);
     ++S.n_acc;
+    if (rec) rec->accept(hacc, 6, S.y, S.n_acc);
     S.fvalid = false;
     if (!all_finite<Prob>(S.y)) {
       S.status = kSysNonFinite;
@@ -373,24 +410,6 @@ RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
   }
   w1 = Dm1 / Em1;
 }
-
-// Observer of the stages of an RKC step (the adjoint records them): first()
-// sees w_0 and mut_1, stage(j, ...) sees w_{j-1} with the coefficients of
-// stage j before f(w_{j-1}) is formed.  With kStopAtLast the step ends after
-// stage(s, ...), without forming w_s.
-struct NoSink {
-  static constexpr bool kStopAtLast = false;
-  template <class V>
-  RKMI_HD void first(const V&, double) {}
-  template <class V>
-  RKMI_HD void stage(int, const V&, double, double, double, double) {}
-};
-
-// Observer of accepted RKC steps (the adjoint's forward tape).
-struct NoRec {
-  template <class V>
-  RKMI_HD void accept(double, int, const V&, int64_t) {}
-};
 
 // One RKC step of s stages from (y_n, F_n = f(y_n)) into y (Eqs. E:rkc0 - E:rkcs);
 // the coefficients b_j, mu_j, nu_j, mut_j, gt_j are formed stage by stage.
@@ -714,6 +733,9 @@ struct Driver<Prob, kMethodRkck, Rec> {
   static constexpr int N = Prob::N, U = kUnroll<Prob>;
   typename Prob::Lane L;
   RkckState<Prob> S;
+  Rec* rec = nullptr;
+  RKMI_HD const Vec<Prob>& state() const { return S.y; }
+  RKMI_HD int64_t accepted() const { return S.n_acc; }
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
                      const double* y0, const double* g, double* slot) {
     Prob::init(L, prm, g, i, n, slot);
@@ -724,7 +746,7 @@ struct Driver<Prob, kMethodRkck, Rec> {
     return S.t < c.t1;
   }
   RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
-    return rkck_attempt<Prob>(L, prm, c, S, slot);
+    return rkck_attempt<Prob, Rec>(L, prm, c, S, slot, rec);
   }
   RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
     if (y1)
@@ -745,6 +767,8 @@ struct Driver<Prob, kMethodRkc, Rec> {
   typename Prob::Lane L;
   RkcState<Prob> S;
   Rec* rec = nullptr;
+  RKMI_HD const Vec<Prob>& state() const { return S.yn; }
+  RKMI_HD int64_t accepted() const { return S.nstep; }
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
                      const double* y0, const double* g, double* slot) {
     Prob::init(L, prm, g, i, n, slot);

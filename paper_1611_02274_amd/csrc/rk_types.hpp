@@ -64,11 +64,12 @@ struct TapeArgs {
 
 // Arguments of one adjoint launch (device pointers).
 struct AdjointArgs {
+  int method;            // kMethodRkck | kMethodRkc (the method of the taped forward call)
   int64_t n;
   const double* g;       // [P][n]
   const double* prm;     // uniform problem data
   TapeArgs tape;
-  int32_t max_stages;    // bound on the recorded stage counts
+  int32_t max_stages;    // RKC: bound on the recorded stage counts
   const double* w;       // [N][n] dL/dy(t1)
   double* dy0;           // [N][n] dL/dy(t0)
   double* dth;           // [n_theta][n] per-system dL/dtheta

@@ -73,3 +73,11 @@ def adjoint_reverse(n_eq: int, net, n_steps, stage_sum) -> float:
     V = vjp_flops(net)
     N = n_eq
     return float(stage_sum * V + (stage_sum - n_steps) * (10 * N + 4) + n_steps * (4 * N + 1))
+
+
+def adjoint_reverse_rkck(n_eq: int, net, n_steps) -> float:
+    """Flops of the RKCK reverse sweep over n_steps accepted steps (total over
+    all systems): per step six VJPs, kbar_i = c_i lambda (6N), u = h kbar_i
+    (6N), ybar += zbar (6N) and kbar_j += b_ij zbar over the 15 couplings (30N
+    fused pairs counted as 2 flops each: 30N)."""
+    return float(n_steps * (6 * vjp_flops(net) + 48 * n_eq))

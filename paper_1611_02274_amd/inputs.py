@@ -217,6 +217,8 @@ WORKLOADS = {
                            (900.0, 2800.0)),
     "net13_adjoint": Workload("net13_adjoint", "rkc", "net13", 1 << 16, 0.0, 1e-6, 1e-8, 1e-12,
                               5005, (1000.0, 2500.0)),
+    "net13_adjoint_rkck": Workload("net13_adjoint_rkck", "rkck", "net13", 1 << 16, 0.0, 1e-6,
+                                   1e-8, 1e-12, 5005, (1000.0, 2500.0)),
 }
 
 

@@ -9,7 +9,7 @@ import pytest
 from paper_1611_02274_amd import inputs as I
 
 
-def _host_adjoint(prob, y0, g, w, t0, t1, rtol, atol, cap, K, max_stages=None):
+def _host_adjoint(prob, y0, g, w, t0, t1, rtol, atol, cap, K, max_stages=None, method=1):
     from paper_1611_02274_amd import _lib
     L = _lib.lib()
     n = y0.shape[1]
@@ -26,19 +26,20 @@ def _host_adjoint(prob, y0, g, w, t0, t1, rtol, atol, cap, K, max_stages=None):
     st = np.zeros(n, dtype=np.int32)
     stats = np.zeros((6, n), dtype=np.int32)
     f = L.rkmi_test_host_taped
-    f.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
-                  C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
-                  C.c_size_t, C.c_int64, C.c_int32]
-    assert f(prob.handle, n, y0.ctypes.data, y1.ctypes.data, g.ctypes.data, t0, t1, rtol, atol,
+    f.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                  C.c_void_p, C.c_size_t, C.c_int64, C.c_int32]
+    assert f(prob.handle, method, n, y0.ctypes.data, y1.ctypes.data, g.ctypes.data, t0, t1, rtol, atol,
              st.ctypes.data, stats.ctypes.data, base, nb, cap, K) == 0
     ms = int(stats[5].max()) if max_stages is None else max_stages
     dy0 = np.zeros_like(y0)
     dth = np.zeros((prob.n_theta, n))
     ast = np.zeros(n, dtype=np.int32)
     fa = L.rkmi_test_host_adjoint
-    fa.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t, C.c_int64,
-                   C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-    assert fa(prob.handle, n, g.ctypes.data, base, nb, cap, K, ms, w.ctypes.data,
+    fa.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_size_t,
+                   C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                   C.c_void_p]
+    assert fa(prob.handle, method, n, g.ctypes.data, base, nb, cap, K, ms, w.ctypes.data,
               dy0.ctypes.data, dth.ctypes.data, ast.ctypes.data) == 0
     count = np.frombuffer(tape[base - tape.ctypes.data:][:4 * n].tobytes(), dtype=np.int32)
     return y1, st, stats, dy0, dth, ast, count
@@ -103,3 +104,35 @@ def test_tape_overflow_and_stage_bound_give_status_and_nan(orc):
     assert big.any() and (~big).any()
     assert np.all(ast[big] == 4) and np.all(ast[~big] == 0)
     assert np.all(np.isnan(dy0[:, big])) and np.all(np.isfinite(dy0[:, ~big]))
+
+
+@pytest.mark.parametrize("K", [16, 1, 3])
+def test_rkck_network_adjoint_host_equals_oracle(orc, K):
+    """RKCK: the taped forward and the reverse sweep (segments recomputed from
+    checkpoints, stage arguments recomputed per step) on the host reproduce the
+    oracle's store-everything RKCK adjoint bit for bit."""
+    import paper_1611_02274_amd as rk
+    net = I.network_of("net13")
+    y0, g = I.kinetics_inputs(net, 12, 5007, (1000.0, 2500.0))
+    w = I.adjoint_weights(13, 12, 5007)
+    prob, pb = rk.Problem.network(net), orc.network(net)
+    y1, st, stats, dy0, dth, ast, count = _host_adjoint(prob, y0, g, w, 0.0, 3e-8, 1e-8, 1e-12,
+                                                        cap=4096, K=K, method=0)
+    yo, d0, dt, so = orc.rkck_adjoint_batch(pb, y0, g, w, 0.0, 3e-8, 1e-8, 1e-12)
+    assert np.all(ast == 0) and np.array_equal(st, so)
+    assert np.array_equal(count, stats[0]) and count.min() >= 1 and count.max() > 10
+    assert _bits_equal(y1, yo)
+    assert _bits_equal(dy0, d0)
+    assert _bits_equal(dth, dt)
+
+
+def test_rkck_vdp_adjoint_host_equals_oracle(orc):
+    import paper_1611_02274_amd as rk
+    y0, g = I.vdp_inputs(10, 5)
+    w = np.random.default_rng(6).standard_normal((2, 10))
+    prob, pb = rk.Problem.vdp(), orc.vdp()
+    y1, st, stats, dy0, dth, ast, count = _host_adjoint(prob, y0, g, w, 0.0, 2.0, 1e-8, 1e-10,
+                                                        cap=20000, K=7, method=0)
+    yo, d0, dt, so = orc.rkck_adjoint_batch(pb, y0, g, w, 0.0, 2.0, 1e-8, 1e-10)
+    assert np.all(ast == 0)
+    assert _bits_equal(y1, yo) and _bits_equal(dy0, d0) and _bits_equal(dth, dt)

@@ -170,3 +170,83 @@ def test_tape_overflow_status(rk):
     assert np.all(count[over] == -1) and np.all(ast[over] == 4)
     assert np.all(np.isnan(dy0[:, over])) and np.all(np.isfinite(dy0[:, ~over]))
     assert np.all(ast[~over] == 0)
+
+
+def _gpu_adjoint_rkck(rk, prob, y0, g, w, t0, t1, rtol, atol, max_accepted=4096, ckpt_every=16):
+    import torch
+    yd = torch.from_numpy(y0).cuda()
+    gd = torch.from_numpy(g).cuda()
+    y1, st, stats, tape = rk.integrate_rkck_taped(prob, yd, gd, t0, t1, rtol, atol,
+                                                  max_accepted=max_accepted,
+                                                  ckpt_every=ckpt_every)
+    dy0, dth, ast = rk.adjoint_rkck(prob, gd, tape, torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (y1, st, stats, dy0, dth, ast, tape.count)]
+
+
+@pytest.mark.parametrize("problem,n,t1,K", [("net13", 700, 5e-8, 16), ("net13", 130, 2e-8, 3),
+                                            ("net9", 400, 5e-8, 8), ("vdp", 300, 2.0, 16)])
+def test_rkck_adjoint_equals_oracle(rk, orc, problem, n, t1, K):
+    """The RKCK discrete adjoint (taped forward, reverse sweep recomputing
+    segments and stage arguments) against the oracle's store-everything RKCK
+    adjoint, over several tiles and a ragged tail."""
+    say(f"case rkck adjoint {problem} n={n} t1={t1} K={K}")
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, 19)
+        prob, pb, atol = rk.Problem.vdp(), orc.vdp(), 1e-10
+        w = np.random.default_rng(19).standard_normal((2, n))
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, 5009, (1000.0, 2500.0))
+        prob, pb, atol = rk.Problem.network(net), orc.network(net), 1e-12
+        w = I.adjoint_weights(net.n_sp, n, 5009)
+    y1, st, stats, dy0, dth, ast, count = _gpu_adjoint_rkck(rk, prob, y0, g, w, 0.0, t1, 1e-8,
+                                                            atol, max_accepted=20000,
+                                                            ckpt_every=K)
+    yo, d0, dt, so = orc.rkck_adjoint_batch(pb, y0, g, w, 0.0, t1, 1e-8, atol)
+    assert np.all(ast == 0) and np.array_equal(st, so)
+    assert np.array_equal(count, stats[0])
+    bitwise = float((dy0.view(np.int64) == d0.view(np.int64)).all(0).mean())
+    say("rkck adjoint parity", dict(dy0_rel=_rel(dy0, d0), dth_rel=_rel(dth, dt), bitwise=bitwise))
+    assert _rel(y1, yo) <= 1e-9
+    assert _rel(dy0, d0) <= 1e-9 and _rel(dth, dt) <= 1e-9
+
+
+def test_rkck_autograd_and_fd(rk, orc):
+    """rkck_solve: loss.backward() gives the RKCK adjoint kernel's gradients;
+    on a few systems they agree with central differences (h = 1e-6) of the
+    frozen RKCK step sequence, normwise to 1e-6."""
+    import torch
+    say("case rkck autograd")
+    net = I.network_of("net13")
+    n = 96
+    y0, g = I.kinetics_inputs(net, n, 37, (1000.0, 2500.0))
+    w = I.adjoint_weights(13, n, 37)
+    prob, pb = rk.Problem.network(net), orc.network(net)
+    yd = torch.from_numpy(y0).cuda().requires_grad_(True)
+    gd = torch.from_numpy(g).cuda()
+    lnA = torch.from_numpy(net.lnA.copy()).cuda().requires_grad_(True)
+    y1, st, stats = rk.rkck_solve(prob, yd, gd, 0.0, 5e-8, 1e-8, 1e-12, lnA=lnA, max_accepted=8)
+    (torch.from_numpy(w).cuda() * y1).sum().backward()
+    _, _, _, tape = rk.integrate_rkck_taped(prob, yd.detach(), gd, 0.0, 5e-8, 1e-8, 1e-12)
+    dy0, dth, ast = rk.adjoint_rkck(prob, gd, tape, torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    assert int(ast.abs().sum()) == 0
+    assert torch.equal(yd.grad, dy0)
+    assert torch.allclose(lnA.grad, dth.sum(1), rtol=1e-12, atol=0)
+    gy, ga = yd.grad.cpu().numpy(), dth.cpu().numpy()
+    cols = np.arange(0, net.n_rx, 4)
+    for i in (0, 41, 95):
+        gi, yi, wi = g[:, i], y0[:, i], w[:, i]
+        _, _, _, hs = orc.rkck_solve_rec(pb, gi, yi, 0.0, 5e-8, 1e-8, 1e-12)
+
+        def loss(p, yy):
+            return float(np.dot(wi, orc.rkck_replay(p, gi, yy, 0.0, hs)))
+        e = 1e-6
+        fy = np.array([(loss(pb, yi + e * np.eye(13)[m]) - loss(pb, yi - e * np.eye(13)[m])) / (2 * e)
+                       for m in range(13)])
+        fa = np.array([(loss(pb.with_lnA(net.lnA + e * np.eye(net.n_rx)[j]), yi) -
+                        loss(pb.with_lnA(net.lnA - e * np.eye(net.n_rx)[j]), yi)) / (2 * e)
+                       for j in cols])
+        assert _rel(gy[:, i], fy) <= 1e-6
+        assert _rel(ga[cols, i], fa) <= 1e-6
