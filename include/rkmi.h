@@ -258,8 +258,7 @@ int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double *g, const void *tap
                    void *stream);
 
 /* Workspace bytes of rk_adjoint_rkck: per system 12 N doubles (the six stage
- * arguments and their adjoint stage increments) and ckpt_every states (0 on
- * bad arguments). */
+ * arguments and their adjoints) and ckpt_every states (0 on bad arguments). */
 size_t rk_adjoint_rkck_workspace_bytes(rk_problem p, int64_t n_sys, int32_t ckpt_every);
 
 /* Reverse sweep over a tape from rk_integrate_rkck_taped; arguments as for

@@ -416,8 +416,8 @@ int rk_integrate_rkck_taped(rk_problem p, int64_t n_sys, const double* y0, doubl
 namespace {
 
 // Adjoint workspace: per 64 systems one block of per-lane columns (RKC:
-// max_stages stage records of N + 4 doubles; RKCK: 12 N doubles), plus
-// ckpt_every step-start states.
+// max_stages stage records of N + 4 doubles; RKCK: the six stage arguments and
+// their adjoints, 12 N doubles), plus ckpt_every step-start states.
 size_t adjoint_ws_bytes(int method, rk_problem p, int64_t n_sys, int32_t max_stages,
                         int32_t ckpt_every) {
   if (!p || n_sys <= 0 || ckpt_every < 1) return 0;

@@ -26,7 +26,7 @@
 //     u = h kbar_i,  zbar = J(z_i)^T u,  theta^ += (df/dtheta)(z_i)^T u,
 //     ybar += zbar,  kbar_j += b_ij zbar (j < i);
 // ybar is lambda for the step before.  The reverse sweep recomputes a step's
-// stage arguments z_i into the lane's columns, next to the kbar_i.
+// stage arguments z_i into the lane's columns, next to the zbar_i.
 #pragma once
 
 #include "rk_launch.hpp"
@@ -132,7 +132,7 @@ struct RkckStageRecorder {
 };
 
 // Rows of a lane's adjoint columns.  RKC: max_stages stage records, K step
-// starts.  RKCK: six stage arguments z_i, six kbar_i, K step starts.
+// starts.  RKCK: six stage arguments z_i, their adjoints zbar_i, K step starts.
 template <class Prob, int Method>
 RKMI_HD int64_t adjoint_rows(int max_stages, int K) {
   if (Method == kMethodRkck) return (int64_t)12 * Prob::N + (int64_t)K * Prob::N;
@@ -296,7 +296,7 @@ RKMI_HD int32_t adjoint_system_rkck(const typename Prob::Params& prm, int64_t n,
   for (int q = 0; q < NT; ++q) th[q] = 0.0;
   int32_t st = M < 0 ? kSysTape : kSysOk;
   double* const zc = col;                                 // z_1..z_6
-  double* const kc = col + (int64_t)6 * N * kLdsStride;   // kbar_1..kbar_6
+  double* const zbc = col + (int64_t)6 * N * kLdsStride;  // zbar_1..zbar_6
   double* const ys = col + (int64_t)12 * N * kLdsStride;  // step starts of a segment
   for (int64_t seg = M > 0 ? (M - 1) / T.K : -1; st == kSysOk && seg >= 0; --seg) {
     const int64_t k0 = seg * T.K;
@@ -329,30 +329,28 @@ RKMI_HD int32_t adjoint_system_rkck(const typename Prob::Params& prm, int64_t n,
         RkckStageRecorder<N> R{zc};
         rkck_trial<Prob, RkckStageRecorder<N>>(L, prm, y, F, hk, yt, ye, slot, &R);
       }
-      V yb, u, jtu, z;
-      for (int s6 = 0; s6 < 6; ++s6) {
-        double* const kb = kc + (int64_t)s6 * N * kLdsStride;
-#pragma unroll
-        for (int r = 0; r < N; ++r) kb[r * kLdsStride] = ck::kC[s6] * lam[r];
-      }
+      // kbar_i = c_i lambda + sum_{i' > i} b_i'i zbar_i' is formed when stage i
+      // is reached (accumulated from i' = 6 down, the order in which the
+      // transposed sweep adds the terms), from the zbar_i' kept in the lane's
+      // columns
+      V yb, u, z, zb;
 #pragma unroll
       for (int r = 0; r < N; ++r) yb[r] = lam[r];
       for (int si = 5; si >= 0; --si) {
-        const double* const kb = kc + (int64_t)si * N * kLdsStride;
         const double* const zi = zc + (int64_t)si * N * kLdsStride;
 #pragma unroll
         for (int r = 0; r < N; ++r) {
-          u[r] = hk * kb[r * kLdsStride];
+          double kb = ck::kC[si] * lam[r];
+          for (int ip = 5; ip > si; --ip) kb += ck::kB[ip][si] * zbc[((int64_t)ip * N + r) * kLdsStride];
+          u[r] = hk * kb;
           z[r] = zi[r * kLdsStride];
         }
-        Prob::vjp(L, prm, z, u, jtu, th);
+        Prob::vjp(L, prm, z, u, zb, th);
+        double* const zbi = zbc + (int64_t)si * N * kLdsStride;
 #pragma unroll
-        for (int r = 0; r < N; ++r) yb[r] += jtu[r];
-        for (int j = 0; j < si; ++j) {
-          double* const kj = kc + (int64_t)j * N * kLdsStride;
-          const double b = ck::kB[si][j];
-#pragma unroll
-          for (int r = 0; r < N; ++r) kj[r * kLdsStride] += b * jtu[r];
+        for (int r = 0; r < N; ++r) {
+          yb[r] += zb[r];
+          zbi[r * kLdsStride] = zb[r];
         }
       }
       lam = yb;
