@@ -15,7 +15,7 @@ from . import build as _build
 
 _lib = None
 
-VDP, LINEAR, MASS_ACTION = 1, 2, 3
+VDP, LINEAR, MASS_ACTION, PLEIADES = 1, 2, 3, 4
 OK, NONFINITE, HMIN, MAXSTEPS = 0, 1, 2, 3
 NSTATS = 6
 ST_ACCEPT, ST_REJECT, ST_RHS, ST_SR_CALLS, ST_POW_ITERS, ST_MAX_STAGES = range(6)
@@ -156,6 +156,11 @@ def linear(A):
 
 def network(net):
     return Problem(MASS_ACTION, net.n_sp, 2, net=net)
+
+
+def pleiades():
+    """The seven-body Pleiades problem (28 unknowns, no per-system parameters)."""
+    return Problem(PLEIADES, 28, 0)
 
 
 def _vec(x, n=None):

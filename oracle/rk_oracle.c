@@ -77,8 +77,16 @@ static int check_problem(const orc_problem *pb) {
       (pb->n_rx <= 0 || pb->n_rx > ORC_MAXR || pb->n_param < 2 || !pb->reac || !pb->prod ||
        !pb->lnA || !pb->beta || !pb->Ea || !pb->Keq || !pb->W))
     return -1;
-  if (pb->kind != ORC_VDP && pb->kind != ORC_LINEAR && pb->kind != ORC_MASS_ACTION) return -1;
+  if (pb->kind == ORC_PLEIADES && pb->n_eq != 28) return -1;
+  if (pb->kind != ORC_VDP && pb->kind != ORC_LINEAR && pb->kind != ORC_MASS_ACTION &&
+      pb->kind != ORC_PLEIADES)
+    return -1;
   return 0;
+}
+
+/* Problems with vector-Jacobian products (every kind but Pleiades). */
+static int check_vjp_problem(const orc_problem *pb) {
+  return (check_problem(pb) || pb->kind == ORC_PLEIADES) ? -1 : 0;
 }
 
 /* Arrhenius rate coefficient k = A T^beta exp(-E/T) (Sec. 4.2), evaluated in
@@ -115,6 +123,31 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
       double s = 0.0;
       for (int j = 0; j < N; ++j) s += pb->A[i * N + j] * y[j];
       f[i] = s;
+    }
+  } else if (pb->kind == ORC_PLEIADES) {
+    /* Pleiades problem (Sec. 4.1): seven bodies of mass m_i = i (1-based) in the
+     * plane, state (x_1..x_7, y_1..y_7, x_1'..x_7', y_1'..y_7'); z'' = f(z) as
+     * the 28 first-order equations (z, w)' = (w, f(z)):
+     *   x_i'' = sum_{j != i} m_j (x_j - x_i) / r_ij,  y_i'' likewise,
+     *   r_ij = ((x_i - x_j)^2 + (y_i - y_j)^2)^(3/2).
+     * Readings: the y difference is squared (the printed formula drops the
+     * square); the 3/2 power is d2 * sqrt(d2) with d2 the sum of squares; the
+     * division by r_ij is a multiplication by 1 / r_ij; each sum runs over j in
+     * increasing order from zero. */
+    const double *x = y, *yy = y + 7;
+    for (int i = 0; i < 14; ++i) f[i] = y[14 + i];
+    for (int i = 0; i < 7; ++i) {
+      double ax = 0.0, ay = 0.0;
+      for (int j = 0; j < 7; ++j) {
+        if (j == i) continue;
+        const double mj = (double)(j + 1);
+        const double d2 = (x[i] - x[j]) * (x[i] - x[j]) + (yy[i] - yy[j]) * (yy[i] - yy[j]);
+        const double rinv = 1.0 / (d2 * sqrt(d2));
+        ax += (mj * (x[j] - x[i])) * rinv;
+        ay += (mj * (yy[j] - yy[i])) * rinv;
+      }
+      f[14 + i] = ax;
+      f[21 + i] = ay;
     }
   } else {
     /* Species equations of Sec. 4.2 at constant T: dY_k/dt = W_k omega_k / rho,
@@ -220,7 +253,7 @@ int orc_rhs(const orc_problem *pb, const double *g, double t, const double *y, d
 
 int orc_rhs_vjp(const orc_problem *pb, const double *g, const double *y, const double *u,
                 double *jtu, double *dtheta) {
-  if (check_problem(pb)) return -1;
+  if (check_vjp_problem(pb)) return -1;
   orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
   if (!S) return -2;
   sys_init(S, pb, g);
@@ -939,7 +972,7 @@ int orc_rkc_replay(const orc_problem *pb, const double *g, const double *y0, dou
 int orc_rkc_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
                            double t0, int64_t n_steps, const double *h, const int32_t *s,
                            const double *w, double *dy0, double *dtheta) {
-  if (check_problem(pb)) return -1;
+  if (check_vjp_problem(pb)) return -1;
   const int N = pb->n_eq;
   const int NT = orc_n_theta(pb);
   int smax = 2;
@@ -1051,7 +1084,7 @@ int orc_rkck_replay(const orc_problem *pb, const double *g, const double *y0, do
 int orc_rkck_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
                             double t0, int64_t n_steps, const double *h, const double *w,
                             double *dy0, double *dtheta) {
-  if (check_problem(pb)) return -1;
+  if (check_vjp_problem(pb)) return -1;
   const int N = pb->n_eq;
   const int NT = orc_n_theta(pb);
   orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
@@ -1169,7 +1202,7 @@ int orc_rkc_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, co
                           double t0, double t1, double rtol, double atol, int64_t max_steps,
                           const double *w, double *y1, double *dy0, double *dtheta,
                           int32_t *status, int n_threads) {
-  if (check_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
+  if (check_vjp_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq, P = pb->n_param, NT = orc_n_theta(pb);
   int nt = n_threads > 0 ? n_threads : orc_max_threads();
   int failed = 0;
@@ -1205,7 +1238,7 @@ int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, c
                            double t0, double t1, double rtol, double atol, int64_t max_steps,
                            const double *w, double *y1, double *dy0, double *dtheta,
                            int32_t *status, int n_threads) {
-  if (check_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
+  if (check_vjp_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq, P = pb->n_param, NT = orc_n_theta(pb);
   int nt = n_threads > 0 ? n_threads : orc_max_threads();
   int failed = 0;

@@ -29,7 +29,7 @@
 #define ORC_MAXR 2048     /* max reactions */
 #define ORC_MAXP 8        /* max per-system parameters */
 
-enum { ORC_VDP = 1, ORC_LINEAR = 2, ORC_MASS_ACTION = 3 };
+enum { ORC_VDP = 1, ORC_LINEAR = 2, ORC_MASS_ACTION = 3, ORC_PLEIADES = 4 };
 
 /* per-system status */
 enum { ORC_OK = 0, ORC_NONFINITE = 1, ORC_HMIN = 2, ORC_MAXSTEPS = 3 };
@@ -46,9 +46,10 @@ enum {
 };
 
 typedef struct {
-  int kind;            /* ORC_VDP | ORC_LINEAR | ORC_MASS_ACTION */
-  int n_eq;            /* N */
-  int n_param;         /* entries of g per system: vdp 1 (mu), linear 0, mass action 2 (T, rho) */
+  int kind;            /* ORC_VDP | ORC_LINEAR | ORC_MASS_ACTION | ORC_PLEIADES */
+  int n_eq;            /* N (Pleiades: 28) */
+  int n_param;         /* entries of g per system: vdp 1 (mu), linear 0, mass action 2 (T, rho),
+                          Pleiades 0 */
   const double *A;     /* ORC_LINEAR: f = A y, A row-major [N][N] */
   int n_rx;            /* ORC_MASS_ACTION: reactions */
   const int32_t *reac; /* [n_rx][2] species index per reactant slot, -1 = empty */

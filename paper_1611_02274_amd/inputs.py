@@ -188,12 +188,37 @@ def vdp_inputs(n: int, seed: int):
     return np.ascontiguousarray(y0), np.ascontiguousarray(mu[None, :])
 
 
+# Seed of the synthetic seven-body base configuration of the Pleiades workload
+# (the problem's own initial conditions are not part of the paper).
+PLEIADES_BASE_SEED = 716
+
+
+def pleiades_base(seed: int = PLEIADES_BASE_SEED) -> np.ndarray:
+    """A seeded seven-body configuration [28]: bodies near a ring (angle
+    2 pi i / 7 + U[-0.3, 0.3], radius U[1.5, 4]) moving tangentially with
+    speed U[0.5, 1.5] * sqrt(28 / r) / 2; layout (x_1..7, y_1..7, x'_1..7, y'_1..7)."""
+    rng = np.random.default_rng(seed)
+    ang = 2.0 * np.pi * np.arange(7) / 7.0 + rng.uniform(-0.3, 0.3, 7)
+    rad = rng.uniform(1.5, 4.0, 7)
+    v = rng.uniform(0.5, 1.5, 7) * np.sqrt(28.0 / rad) * 0.5
+    return np.concatenate([rad * np.cos(ang), rad * np.sin(ang), -v * np.sin(ang), v * np.cos(ang)])
+
+
+def pleiades_inputs(n: int, seed: int, rel: float = 1e-2):
+    """(y0 [28, n], None): the base configuration with every component of every
+    system multiplied by 1 + rel * U[-1, 1] (the paper's randomly perturbed
+    initial conditions, Sec. 4.1)."""
+    rng = np.random.default_rng(seed)
+    f = 1.0 + rel * rng.uniform(-1.0, 1.0, (28, n))
+    return np.ascontiguousarray(pleiades_base()[:, None] * f), None
+
+
 # ---------------------------------------------------------------- workloads
 @dataclasses.dataclass
 class Workload:
     name: str
     method: str            # "rkck" | "rkc"
-    problem: str           # "vdp" | "net9" | "net13" | "net32" | "net53"
+    problem: str           # "vdp" | "pleiades" | "net9" | "net13" | "net32" | "net53"
     n: int
     t0: float
     t1: float
@@ -215,6 +240,9 @@ WORKLOADS = {
                           (900.0, 2800.0)),
     "net53_rkck": Workload("net53_rkck", "rkck", "net53", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3003,
                            (900.0, 2800.0)),
+    # ten global steps of 0.1 over [0, 1], each a restart (Sec. 4.1); eps = 1e-10
+    "pleiades_rkck": Workload("pleiades_rkck", "rkck", "pleiades", 1 << 18, 0.0, 1.0, 1e-10, 0.0,
+                              6006, launch=dict(schedule=1)),
     "net13_adjoint": Workload("net13_adjoint", "rkc", "net13", 1 << 16, 0.0, 1e-6, 1e-8, 1e-12,
                               5005, (1000.0, 2500.0)),
     "net13_adjoint_rkck": Workload("net13_adjoint_rkck", "rkck", "net13", 1 << 16, 0.0, 1e-6,
@@ -233,6 +261,8 @@ def workload_inputs(w: Workload, n: int | None = None):
     n = w.n if n is None else n
     if w.problem == "vdp":
         return vdp_inputs(n, w.seed)
+    if w.problem == "pleiades":
+        return pleiades_inputs(n, w.seed)
     return kinetics_inputs(network_of(w.problem), n, w.seed, w.T_range)
 
 
