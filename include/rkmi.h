@@ -116,6 +116,17 @@ const char *rk_last_error(void);
  * with rk_problem_destroy. */
 int rk_problem_create_vdp(rk_problem *out);
 
+/* The Pleiades problem (Sec. 4.1): seven bodies of mass m_i = i in the plane,
+ * 28 unknowns per system in the order x_1..x_7, y_1..y_7, x_1'..x_7',
+ * y_1'..y_7'; f = (velocities, accelerations) with
+ *   x_i'' = sum_{j != i} m_j (x_j - x_i) / r_ij,  y_i'' likewise,
+ *   r_ij = ((x_i - x_j)^2 + (y_i - y_j)^2)^(3/2),
+ * the 3/2 power formed as d2 sqrt(d2) and the division as a multiplication by
+ * the pair's reciprocal.  No per-system parameters (pass g = NULL).  Its
+ * vectors live in workspace columns: every schedule needs rk_workspace_bytes.
+ * No adjoint (RK_EUNSUPPORTED). */
+int rk_problem_create_pleiades(rk_problem *out);
+
 /* Mass-action network described by *desc (host memory, copied).  The network
  * topology must have been compiled into the library (see the package's code
  * generator); RK_EUNSUPPORTED otherwise. */

@@ -40,6 +40,12 @@ class Problem:
         return cls(h, "vdp")
 
     @classmethod
+    def pleiades(cls) -> "Problem":
+        h = C.c_void_p()
+        _lib.check(_lib.lib().rk_problem_create_pleiades(C.byref(h)))
+        return cls(h, "pleiades")
+
+    @classmethod
     def network(cls, net) -> "Problem":
         import numpy as np
         keep = dict(

@@ -65,6 +65,7 @@ def lib():
         L.rk_version.restype = C.c_int
         L.rk_last_error.restype = C.c_char_p
         L.rk_problem_create_vdp.argtypes = [C.POINTER(vp)]
+        L.rk_problem_create_pleiades.argtypes = [C.POINTER(vp)]
         L.rk_problem_create_mass_action.argtypes = [C.POINTER(MechDesc), C.POINTER(vp)]
         L.rk_problem_destroy.argtypes = [vp]
         L.rk_problem_destroy.restype = None

@@ -24,6 +24,9 @@ extern "C" int rkmi_vdp_taped(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t
 extern "C" int rkmi_vdp_taped_host(const rkmi::LaunchArgs* a, const rkmi::TapeArgs* t);
 extern "C" int rkmi_vdp_adjoint(const rkmi::AdjointArgs* a, void* s);
 extern "C" int rkmi_vdp_adjoint_host(const rkmi::AdjointArgs* a);
+extern "C" int rkmi_pleiades_launch(const rkmi::LaunchArgs* a, void* s);
+extern "C" int rkmi_pleiades_host(const rkmi::LaunchArgs* a);
+extern "C" int64_t rkmi_pleiades_workspace(int method, int schedule, int64_t n);
 
 namespace rkmi {
 extern const GenEntry kGenRegistry[];
@@ -49,7 +52,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-enum Kind { kVdp = 1, kMassAction = 3 };
+enum Kind { kVdp = 1, kMassAction = 3, kPleiades = 4 };
 
 }  // namespace
 
@@ -256,6 +259,23 @@ int rk_problem_create_vdp(rk_problem* out) {
   p->taped_host = rkmi_vdp_taped_host;
   p->adjoint = rkmi_vdp_adjoint;
   p->adjoint_host = rkmi_vdp_adjoint_host;
+  *out = p;
+  return RK_OK;
+}
+
+int rk_problem_create_pleiades(rk_problem* out) {
+  g_err.clear();
+  if (!out) return fail(RK_EINVAL, "out is NULL");
+  *out = nullptr;
+  rk_problem p = new (std::nothrow) rk_problem_s();
+  if (!p) return fail(RK_ENOMEM, "out of host memory");
+  p->kind = kPleiades;
+  p->n_eq = 28;
+  p->n_param = 0;
+  p->n_theta = 0;
+  p->launch = rkmi_pleiades_launch;
+  p->host = rkmi_pleiades_host;
+  p->workspace = rkmi_pleiades_workspace;
   *out = p;
   return RK_OK;
 }

@@ -8,7 +8,11 @@ the operations the method must perform as written in the paper, not the
 instructions a kernel happens to issue.
 
 Per-unit counts (N unknowns, NR reactions, S = reactant+product slots in use):
-  right-hand side  van der Pol: 5;  mass action: 5N - 1 + 5NR + S
+  right-hand side  van der Pol: 5;  mass action: 5N - 1 + 5NR + S;
+                   Pleiades: 378 (21 pairs: two differences, squared distance 3,
+                   d2 sqrt(d2) 1; 42 ordered pairs x 2 coordinates: m_j dx, times
+                   1/r, accumulate 3; x_j - x_i is the pair's difference negated --
+                   the 21 square roots and reciprocals are special operations)
   rate setup       mass action: 5NR per system (plus 2NR exp/div specials)
   RKCK attempt     56N + 5 beyond its right-hand sides (stage arguments 30N,
                    k_i = h f 6N, fifth-order sum 8N, error sum 9N, scale 3N)
@@ -30,15 +34,21 @@ import numpy as np
 ST_ACCEPT, ST_REJECT, ST_RHS, ST_SR_CALLS, ST_POW_ITERS, ST_MAX_STAGES = range(6)
 
 
+PLEIADES = "pleiades"      # stands for the Pleiades problem where a network is expected
+
+
 def rhs_flops(net=None) -> int:
     if net is None:
         return 5
+    if isinstance(net, str) and net == PLEIADES:
+        return 21 * 6 + 42 * 2 * 3
+
     slots = int((np.asarray(net.reac) >= 0).sum() + (np.asarray(net.prod) >= 0).sum())
     return 5 * net.n_sp - 1 + 5 * net.n_rx + slots
 
 
 def setup_flops(net=None) -> int:
-    return 0 if net is None else 5 * net.n_rx
+    return 0 if net is None or isinstance(net, str) else 5 * net.n_rx
 
 
 def per_system(method: str, stats: np.ndarray, n_eq: int, net=None) -> np.ndarray:

@@ -318,3 +318,62 @@ def test_cost_order_rejects(rk):
     assert f(prob.handle, 100, yd.data_ptr(), out.data_ptr(), gd.data_ptr(), 0.0, 1e-7, 1e-8,
              1e-12, None, None, ws.data_ptr(), need, C.byref(o), s) == _lib.RK_OK
     torch.cuda.synchronize()
+
+
+def _pleiades_global_steps(fn_step, y0, n_global=10, t0=0.0, t1=1.0):
+    """Ten global steps over [t0, t1], each a restart (Sec. 4.1)."""
+    y, dt, last = y0, (t1 - t0) / n_global, None
+    for k in range(n_global):
+        y, st, stats = fn_step(y, t0 + k * dt, t0 + (k + 1) * dt)
+        last = (st, stats)
+    return y, last[0], last[1]
+
+
+@pytest.mark.parametrize("n,schedule,cost_order", [(4133, 1, 0), (4133, 2, 0), (1000, 1, 1),
+                                                   (65, 2, 1)])
+def test_pleiades_rkck(rk, orc, n, schedule, cost_order):
+    """The Pleiades problem (28 unknowns in workspace columns) under RKCK at
+    eps = 1e-10 over the ten global steps of [0, 1]: every schedule equals the
+    oracle step by step."""
+    import torch
+    say(f"case pleiades n={n} schedule={schedule} cost_order={cost_order}")
+    y0, _ = I.pleiades_inputs(n, 6006)
+    prob, pb = rk.Problem.pleiades(), orc.pleiades()
+
+    def gpu_step(y, a, b):
+        yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+        y1, st, stats = rk.integrate_rkck(prob, yd, None, a, b, 1e-10, 0.0, out=yd,
+                                          schedule=schedule, cost_order=cost_order)
+        torch.cuda.synchronize()
+        return y1.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy()
+
+    def orc_step(y, a, b):
+        return orc.rkck_batch(pb, y, None, a, b, 1e-10, 0.0)
+
+    yg, sg, stg = _pleiades_global_steps(gpu_step, y0)
+    yo, so, sto = _pleiades_global_steps(orc_step, y0)
+    compare(yg, sg, stg, yo, so, sto, 1e-10, f"pleiades n={n}")
+
+
+def test_pleiades_full_size_sampled(rk, orc):
+    """The 2^18-system Pleiades workload in the benchmark's launch: ten global
+    steps on the GPU; the oracle recomputes a spread sample of 256 systems."""
+    import torch
+    w = I.WORKLOADS["pleiades_rkck"]
+    say(f"case full-size {w.name} n={w.n}")
+    y0, _ = I.workload_inputs(w)
+    prob, pb = rk.Problem.pleiades(), orc.pleiades()
+    yd = torch.from_numpy(y0).cuda()
+
+    def gpu_step(y, a, b):
+        y1, st, stats = rk.integrate_rkck(prob, y, None, a, b, w.rtol, w.atol, out=y, **w.launch)
+        return y1, st, stats
+    yg, sg, stg = _pleiades_global_steps(gpu_step, yd, t0=w.t0, t1=w.t1)
+    torch.cuda.synchronize()
+    yg, sg, stg = yg.cpu().numpy(), sg.cpu().numpy(), stg.cpu().numpy()
+    idx = np.unique(np.linspace(0, w.n - 1, 256).astype(np.int64))
+    yo, so, sto = _pleiades_global_steps(
+        lambda y, a, b: orc.rkck_batch(pb, y, None, a, b, w.rtol, w.atol),
+        np.ascontiguousarray(y0[:, idx]), t0=w.t0, t1=w.t1)
+    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, 1e-10, "full pleiades sample")
+    assert np.all(sg == 0)

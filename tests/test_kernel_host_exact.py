@@ -20,7 +20,7 @@ def _host_run(prob, method, y0, g, t0, t1, rtol, atol, max_steps=0):
                   C.c_int64]
     f.restype = C.c_int
     y0 = np.ascontiguousarray(y0, dtype=np.float64)
-    g = np.ascontiguousarray(g, dtype=np.float64)
+    g = np.ascontiguousarray(g if g is not None else np.zeros((1, 1)), dtype=np.float64)
     n = y0.shape[1]
     y1 = np.zeros_like(y0)
     st = np.zeros(n, dtype=np.int32)
@@ -43,6 +43,10 @@ CASES = [
     ("rkc", "net53", 12, 3003, 0.0, 1e-6, 1e-8, 1e-12, (900.0, 2800.0)),
     ("rkck", "net32", 8, 31, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
     ("rkck", "net53", 8, 3003, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
+    # the Pleiades problem (28 unknowns in slot columns), one global step
+    ("rkck", "pleiades", 24, 6006, 0.0, 0.1, 1e-10, 0.0, None),
+    ("rkck", "pleiades", 8, 6007, 0.5, 0.6, 1e-12, 1e-14, None),
+    ("rkc", "pleiades", 8, 6008, 0.0, 0.1, 1e-8, 1e-10, None),
 ]
 
 
@@ -53,6 +57,9 @@ def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, 
     if problem == "vdp":
         y0, g = I.vdp_inputs(n, seed)
         prob, pb = rk.Problem.vdp(), orc.vdp()
+    elif problem == "pleiades":
+        y0, g = I.pleiades_inputs(n, seed)
+        prob, pb = rk.Problem.pleiades(), orc.pleiades()
     else:
         net = I.network_of(problem)
         y0, g = I.kinetics_inputs(net, n, seed, T_range)
