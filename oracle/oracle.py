@@ -90,6 +90,12 @@ def lib():
             "orc_rkck_replay": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _dp]),
             "orc_rkck_replay_adjoint": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _dp,
                                                   _dp, _dp]),
+            "orc_rkck_batch_carry": (C.c_int, [P, C.c_int64, _dp, _dp, _dp, C.c_double,
+                                               C.c_double, C.c_double, C.c_double, C.c_int64,
+                                               _ip, _ip, _dp, C.c_int]),
+            "orc_rkc_batch_carry": (C.c_int, [P, C.c_int64, _dp, _dp, _dp, C.c_double,
+                                              C.c_double, C.c_double, C.c_double, C.c_int64,
+                                              _ip, _ip, _dp, C.c_int]),
             "orc_max_threads": (C.c_int, []),
             "orc_cr_exp": (C.c_double, [C.c_double]),
             "orc_cr_log": (C.c_double, [C.c_double]),
@@ -352,6 +358,43 @@ def _batch(fn, pb, y0, g, t0, t1, rtol, atol, max_steps, n_threads):
             max_steps, _i(status), _i(stats), n_threads)
     assert rc == 0, rc
     return y1, status, stats
+
+
+CARRY_ROWS = 7      # valid, h, h_prev, err_prev, sigma, nstep, have_prev; then v [N]
+
+
+def carry_init(pb, n):
+    """A carried-state array [CARRY_ROWS + N, n] asking every system to restart."""
+    return np.zeros((CARRY_ROWS + pb.n_eq, n))
+
+
+def _batch_carry(fn, pb, y0, g, carry, t0, t1, rtol, atol, max_steps, n_threads):
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    n = y0.shape[1]
+    g = np.ascontiguousarray(g, dtype=np.float64) if g is not None else np.zeros((0, n))
+    assert carry.shape == (CARRY_ROWS + pb.n_eq, n) and carry.flags.c_contiguous
+    assert carry.dtype == np.float64
+    y1 = np.zeros_like(y0)
+    status = np.zeros(n, dtype=np.int32)
+    stats = np.zeros((NSTATS, n), dtype=np.int32)
+    rc = fn(pb.ptr, n, _d(y0), _d(g) if g.size else None, _d(y1), t0, t1, rtol, atol,
+            max_steps, _i(status), _i(stats), _d(carry), n_threads)
+    assert rc == 0, rc
+    return y1, status, stats
+
+
+def rkck_batch_carry(pb, y0, g, carry, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS,
+                     n_threads=0):
+    """RKCK with the controller state carried in `carry` (updated in place)."""
+    return _batch_carry(lib().orc_rkck_batch_carry, pb, y0, g, carry, t0, t1, rtol, atol,
+                        max_steps, n_threads)
+
+
+def rkc_batch_carry(pb, y0, g, carry, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS,
+                    n_threads=0):
+    """RKC with the controller state carried in `carry` (updated in place)."""
+    return _batch_carry(lib().orc_rkc_batch_carry, pb, y0, g, carry, t0, t1, rtol, atol,
+                        max_steps, n_threads)
 
 
 def rkck_batch(pb, y0, g, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, n_threads=0):

@@ -425,7 +425,7 @@ static void rec_push(step_rec *r, double h, int s) {
  * that exhausts max_steps attempts (the listing has no exit for these). */
 static int rkck_solve_impl(const orc_problem *pb, const double *g, const double *y0, double *y1,
                            double t0, double t1, double rtol, double atol, int64_t max_steps,
-                           int32_t *stats, step_rec *rec) {
+                           int32_t *stats, step_rec *rec, double *carry) {
   if (check_problem(pb) || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
   if (!S) return -2;
@@ -437,6 +437,10 @@ static int rkck_solve_impl(const orc_problem *pb, const double *g, const double 
   const double hmax = fabs(t1 - t0);
   const double hmin = 1.0e-20;
   double h = 0.5 * fabs(t1 - t0);
+  /* a carried state brings the step the previous call would have taken next */
+  if (carry && carry[ORC_CARRY_VALID] != 0.0) h = carry[ORC_CARRY_H];
+  double h_want = h;
+  int cut = 0;
   int fvalid = 0, status = ORC_OK;
   int64_t attempts = 0, n_acc = 0, n_rej = 0, n_rhs = 0;
   while (t < t1) {
@@ -444,6 +448,7 @@ static int rkck_solve_impl(const orc_problem *pb, const double *g, const double 
       status = ORC_MAXSTEPS;
       break;
     }
+    h_want = h;
     h = fmin(t1 - t, h);
     if (!fvalid) {
       rhs(S, t, y, F);
@@ -464,6 +469,7 @@ static int rkck_solve_impl(const orc_problem *pb, const double *g, const double 
         break;
       }
     } else {
+      cut = h < h_want;
       rec_push(rec, h, 6);
       t += h;
       h = hnew;
@@ -475,6 +481,10 @@ static int rkck_solve_impl(const orc_problem *pb, const double *g, const double 
         break;
       }
     }
+  }
+  if (carry) {
+    carry[ORC_CARRY_VALID] = status == ORC_OK ? 1.0 : 0.0;
+    carry[ORC_CARRY_H] = cut ? h_want : h;
   }
   for (int i = 0; i < N; ++i) y1[i] = y[i];
   if (stats) {
@@ -492,7 +502,7 @@ static int rkck_solve_impl(const orc_problem *pb, const double *g, const double 
 int orc_rkck_solve(const orc_problem *pb, const double *g, const double *y0, double *y1,
                    double t0, double t1, double rtol, double atol, int64_t max_steps,
                    int32_t *stats) {
-  return rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, NULL);
+  return rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, NULL, NULL);
 }
 
 /* As orc_rkck_solve, also recording the accepted step sizes (the first
@@ -502,7 +512,7 @@ int orc_rkck_solve_rec(const orc_problem *pb, const double *g, const double *y0,
                        int32_t *stats, double *rec_h, int64_t rec_cap, int64_t *n_rec) {
   int32_t *rs = rec_h && rec_cap > 0 ? (int32_t *)malloc(sizeof(int32_t) * (size_t)rec_cap) : NULL;
   step_rec r = {rec_h, rs, 0, rs ? rec_cap : 0, 0};
-  int st = rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r);
+  int st = rkck_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r, NULL);
   if (n_rec) *n_rec = r.n;
   free(rs);
   return st;
@@ -788,7 +798,7 @@ double orc_rkc_accept_factor(double err, double err_prev, double h, double h_pre
  * Guards as in the RKCK driver. */
 static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *y0, double *y1,
                           double t0, double t1, double rtol, double atol, int64_t max_steps,
-                          int32_t *stats, step_rec *rec) {
+                          int32_t *stats, step_rec *rec, double *carry) {
   if (check_problem(pb) || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq;
   const int mmax = orc_rkc_mmax(rtol);
@@ -816,13 +826,29 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
   for (int i = 0; i < N; ++i) v[i] = F_n[i];
   double h = 0.0, h_prev = 0.0, err_prev = 0.0, sigma = 0.0;
   int64_t nstep = 0;
-  int first = 1, have_prev = 0;
+  int first = 1, have_prev = 0, cut = 0;
+  double h_want = 0.0;
+  if (carry && carry[ORC_CARRY_VALID] != 0.0) {
+    /* carried controller state (the alternative to the restart): the next
+     * step, the previous step and error, the spectral radius and its
+     * eigenvector, and the accepted-step count that schedules its refresh;
+     * y_n and f(t0, y_n) are this call's */
+    h = carry[ORC_CARRY_H];
+    h_prev = carry[ORC_CARRY_H_PREV];
+    err_prev = carry[ORC_CARRY_ERR_PREV];
+    sigma = carry[ORC_CARRY_SIGMA];
+    nstep = (int64_t)carry[ORC_CARRY_NSTEP];
+    have_prev = carry[ORC_CARRY_HAVE_PREV] != 0.0;
+    for (int i = 0; i < N; ++i) v[i] = carry[ORC_CARRY_ROWS + i];
+    first = 0;
+  }
   while (t < t1) {
     if (attempts >= max_steps) {
       status = ORC_MAXSTEPS;
       break;
     }
     /* stretch the step to the end point when it is within 10% of it */
+    h_want = h;
     if (1.1 * h >= fabs(t1 - t)) h = fabs(t1 - t);
     /* spectral radius at the first step and every 25 accepted steps */
     if (nstep % 25 == 0) {
@@ -885,6 +911,7 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
         break;
       }
     } else {
+      cut = h < h_want;
       t += h;
       nstep++;
       n_acc++;
@@ -905,6 +932,16 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
       }
     }
   }
+  if (carry) {
+    carry[ORC_CARRY_VALID] = status == ORC_OK ? 1.0 : 0.0;
+    carry[ORC_CARRY_H] = cut ? h_want : h;
+    carry[ORC_CARRY_H_PREV] = h_prev;
+    carry[ORC_CARRY_ERR_PREV] = err_prev;
+    carry[ORC_CARRY_SIGMA] = sigma;
+    carry[ORC_CARRY_NSTEP] = (double)nstep;
+    carry[ORC_CARRY_HAVE_PREV] = have_prev ? 1.0 : 0.0;
+    for (int i = 0; i < N; ++i) carry[ORC_CARRY_ROWS + i] = v[i];
+  }
   for (int i = 0; i < N; ++i) y1[i] = y_n[i];
   if (stats) {
     stats[ORC_ST_ACCEPT] = (int32_t)n_acc;
@@ -924,7 +961,7 @@ int orc_rkc_solve(const orc_problem *pb, const double *g, const double *y0, doub
                   int32_t *stats, double *rec_h, int32_t *rec_s, int64_t rec_cap,
                   int64_t *n_rec) {
   step_rec r = {rec_h, rec_s, 0, (rec_h && rec_s) ? rec_cap : 0, 0};
-  int st = rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r);
+  int st = rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r, NULL);
   if (n_rec) *n_rec = r.n;
   return st;
 }
@@ -1155,7 +1192,7 @@ static void scatter(double *soa, int64_t n, int64_t i, int rows, const double *i
 static int batch_common(int method, const orc_problem *pb, int64_t n, const double *y0,
                         const double *g, double *y1, double t0, double t1, double rtol,
                         double atol, int64_t max_steps, int32_t *status, int32_t *stats,
-                        int n_threads) {
+                        double *carry, int n_threads) {
   if (check_problem(pb) || n < 0 || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq, P = pb->n_param;
   int nt = n_threads > 0 ? n_threads : orc_max_threads();
@@ -1163,20 +1200,22 @@ static int batch_common(int method, const orc_problem *pb, int64_t n, const doub
   (void)nt;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
   for (int64_t i = 0; i < n; ++i) {
-    double ys[ORC_MAXN], yo[ORC_MAXN], gs[ORC_MAXP];
+    double ys[ORC_MAXN], yo[ORC_MAXN], gs[ORC_MAXP], cs[ORC_CARRY_ROWS + ORC_MAXN];
     int32_t st[ORC_NSTATS];
     gather(y0, n, i, N, ys);
     gather(g, n, i, P, gs);
+    if (carry) gather(carry, n, i, ORC_CARRY_ROWS + N, cs);
+    double *cp = carry ? cs : NULL;
     int rc = (method == 0)
-                 ? orc_rkck_solve(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st)
-                 : orc_rkc_solve(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL,
-                                 NULL, 0, NULL);
+                 ? rkck_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL, cp)
+                 : rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL, cp);
     if (rc < 0) {
 #pragma omp atomic write
       failed = 1;
       continue;
     }
     scatter(y1, n, i, N, yo);
+    if (carry) scatter(carry, n, i, ORC_CARRY_ROWS + N, cs);
     if (status) status[i] = rc;
     if (stats)
       for (int r = 0; r < ORC_NSTATS; ++r) stats[(size_t)r * n + i] = st[r];
@@ -1187,14 +1226,14 @@ static int batch_common(int method, const orc_problem *pb, int64_t n, const doub
 int orc_rkck_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
                    double *y1, double t0, double t1, double rtol, double atol,
                    int64_t max_steps, int32_t *status, int32_t *stats, int n_threads) {
-  return batch_common(0, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats,
+  return batch_common(0, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats, NULL,
                       n_threads);
 }
 
 int orc_rkc_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
                   double *y1, double t0, double t1, double rtol, double atol,
                   int64_t max_steps, int32_t *status, int32_t *stats, int n_threads) {
-  return batch_common(1, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats,
+  return batch_common(1, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats, NULL,
                       n_threads);
 }
 
@@ -1215,7 +1254,7 @@ int orc_rkc_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, co
     gather(g, n, i, P, gs);
     gather(w, n, i, N, ws);
     step_rec r = {NULL, NULL, 0, 0, 1};
-    int rc = rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r);
+    int rc = rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r, NULL);
     int rc2 = (rc >= 0 && r.n <= r.cap)
                   ? orc_rkc_replay_adjoint(pb, gs, ys, t0, r.n, r.h, r.s, ws, d0, dth)
                   : -2;
@@ -1251,7 +1290,7 @@ int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, c
     gather(g, n, i, P, gs);
     gather(w, n, i, N, ws);
     step_rec r = {NULL, NULL, 0, 0, 1};
-    int rc = rkck_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r);
+    int rc = rkck_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r, NULL);
     int rc2 = (rc >= 0 && r.n <= r.cap)
                   ? orc_rkck_replay_adjoint(pb, gs, ys, t0, r.n, r.h, ws, d0, dth)
                   : -2;
@@ -1268,4 +1307,22 @@ int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, c
     if (status) status[i] = rc;
   }
   return failed ? -2 : 0;
+}
+
+/* Batches with the controller state carried between calls: carry [rows][n]
+ * SoA, rows ORC_CARRY_ROWS + N (RKCK uses the first two), updated in place. */
+int orc_rkck_batch_carry(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                         double *y1, double t0, double t1, double rtol, double atol,
+                         int64_t max_steps, int32_t *status, int32_t *stats, double *carry,
+                         int n_threads) {
+  return batch_common(0, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats, carry,
+                      n_threads);
+}
+
+int orc_rkc_batch_carry(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                        double *y1, double t0, double t1, double rtol, double atol,
+                        int64_t max_steps, int32_t *status, int32_t *stats, double *carry,
+                        int n_threads) {
+  return batch_common(1, pb, n, y0, g, y1, t0, t1, rtol, atol, max_steps, status, stats, carry,
+                      n_threads);
 }

@@ -34,6 +34,15 @@ enum { ORC_VDP = 1, ORC_LINEAR = 2, ORC_MASS_ACTION = 3, ORC_PLEIADES = 4 };
 /* per-system status */
 enum { ORC_OK = 0, ORC_NONFINITE = 1, ORC_HMIN = 2, ORC_MAXSTEPS = 3 };
 
+/* Controller state carried from one call to the next instead of the restart
+ * (Sec. 3 notes the alternative), rows of a per-system array followed by the
+ * RKC eigenvector estimate (N rows); RKCK uses VALID and H.  VALID = 0 asks
+ * for the restart; a call leaves VALID = 1 when its system ended OK. */
+enum {
+  ORC_CARRY_VALID = 0, ORC_CARRY_H, ORC_CARRY_H_PREV, ORC_CARRY_ERR_PREV, ORC_CARRY_SIGMA,
+  ORC_CARRY_NSTEP, ORC_CARRY_HAVE_PREV, ORC_CARRY_ROWS
+};
+
 /* per-system statistics, SoA rows */
 enum {
   ORC_ST_ACCEPT = 0,   /* accepted steps */
@@ -143,6 +152,14 @@ int orc_rkck_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, c
                            double t0, double t1, double rtol, double atol, int64_t max_steps,
                            const double *w, double *y1, double *dy0, double *dtheta,
                            int32_t *status, int n_threads);
+int orc_rkck_batch_carry(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                         double *y1, double t0, double t1, double rtol, double atol,
+                         int64_t max_steps, int32_t *status, int32_t *stats, double *carry,
+                         int n_threads);
+int orc_rkc_batch_carry(const orc_problem *pb, int64_t n, const double *y0, const double *g,
+                        double *y1, double t0, double t1, double rtol, double atol,
+                        int64_t max_steps, int32_t *status, int32_t *stats, double *carry,
+                        int n_threads);
 int orc_max_threads(void);
 
 #ifdef __cplusplus
