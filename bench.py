@@ -223,13 +223,21 @@ def ragged_bench(args):
                                 rtol, atol)
     log(f"bench: tuned {tuned}")
 
-    def run(mode, **kw):
+    # --carry: the controller state carried from substep to substep instead of
+    # the restart (zeroed before every run, so each run starts with restarts)
+    carry = ([torch.zeros((rk.carry_rows(p), y.shape[1]), dtype=torch.float64, device=dev)
+              for p, y in zip(probs, ys)] if args.carry else None)
+
+    def run(mode, with_carry=True, **kw):
         for y, y_0 in zip(ys, y0):
             y.copy_(y_0)
+        if carry is not None:
+            for c in carry:
+                c.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
         batch.integrate_rkc(ys, gs, 0.0, dt, K, rtol, atol, mode=mode, slot_map=codes,
-                            status=st, stats=stats, **kw)
+                            status=st, stats=stats, carry=carry if with_carry else None, **kw)
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
@@ -249,13 +257,19 @@ def ragged_bench(args):
         times[mode] = run(mode)
         same = all(np.array_equal(a, b.cpu().numpy()) for a, b in zip(final, ys))
         log(f"bench: {mode} {times[mode]:.3f} s, same bits as persistent: {same}")
+    if carry is not None:
+        times["restart"] = run("persistent", with_carry=False, use_graph=True, **tuned)
+        log(f"bench: persistent with restarts {times['restart']:.3f} s")
     # algorithmic flops: every substep's statistics (substeps one at a time, untimed)
     for y, y_0 in zip(ys, y0):
         y.copy_(y_0)
+    if carry is not None:
+        for c in carry:
+            c.zero_()
     flops = 0.0
     for k in range(K):
         batch.integrate_rkc(ys, gs, k * dt, dt, 1, rtol, atol, mode="persistent", status=st,
-                            stats=stats, **tuned)
+                            stats=stats, carry=carry, **tuned)
         torch.cuda.synchronize()
         flops += sum(FL.total("rkc", s.cpu().numpy(), n.n_sp, n) for s, n in zip(stats, nets))
     tp = times["persistent"]
@@ -269,10 +283,13 @@ def ragged_bench(args):
         "config": {"workload": "ragged_4net", "n_systems": n_total,
                    "networks": "9/19, 13/27, 32/133, 53/325 species/reactions, interleaved",
                    "substeps": K, "dt": dt, "rtol": rtol, "atol": atol, "method": "rkc",
+                   "controller_state": "carried across substeps" if carry is not None
+                                       else "restart at every substep",
                    "schedule": dict(mode="persistent (one launch per substep, HIP graph)",
                                     **tuned),
                    "systems_ok": ok},
-        "gate": {"persistent_s": tp, **{f"{m}_s": times[m] for m in times if m != "persistent"},
+        "gate": {"persistent_s": tp,
+                 **{f"{m}_s": times[m] for m in times if m != "persistent"},
                  "speedup_vs_faster_plain": (min(plain) / tp) if plain else None},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
@@ -292,6 +309,8 @@ def main():
                     help="systems (default: the workload's own count); for profiling runs")
     ap.add_argument("--substeps", type=int, default=2,
                     help="ragged workload: operator-splitting substeps per step")
+    ap.add_argument("--carry", action="store_true",
+                    help="ragged workload: carry the controller state across substeps")
     ap.add_argument("--skip-modes", default="",
                     help="ragged workload: plain forms not to time (interleaved,per_network)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -201,6 +201,31 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
                      int32_t *status, int32_t *stats, void *ws, size_t ws_bytes,
                      const rk_options *opt, void *stream);
 
+/* Controller state carried from one call to the next instead of the restart
+ * at every call (Sec. 3 notes that carrying the integrator's data across
+ * global steps may perform better where the application allows it).  carry:
+ * device [rk_carry_rows(p)][n_sys] doubles, caller-owned, read and rewritten
+ * by the call; rows
+ *   0 valid (0: restart this system, as rk_integrate_*; a call leaves 1 when
+ *     the system ended RK_SYS_OK, else 0), 1 the next step size (the one the
+ *     controller wanted before the final step was cut to t1), 2 the previous
+ *     step, 3 the previous error, 4 the spectral radius, 5 the accepted-step
+ *     count that schedules its refresh every 25 steps, 6 whether a previous
+ *     step exists, 7..7+N-1 the power method's eigenvector estimate;
+ * RKCK uses rows 0 and 1.  y0 and f(t0, y0) are always this call's (the
+ * caller may have changed the state between calls).  Zero the array before
+ * the first call.  Other arguments as rk_integrate_rkck / rk_integrate_rkc
+ * (the cost order's pilot leaves the carried state alone). */
+size_t rk_carry_rows(rk_problem p);
+int rk_integrate_rkck_carry(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                            const double *g, double t0, double t1, double rtol, double atol,
+                            int32_t *status, int32_t *stats, double *carry, void *ws,
+                            size_t ws_bytes, const rk_options *opt, void *stream);
+int rk_integrate_rkc_carry(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                           const double *g, double t0, double t1, double rtol, double atol,
+                           int32_t *status, int32_t *stats, double *carry, void *ws,
+                           size_t ws_bytes, const rk_options *opt, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Discrete adjoints of RKC (Sec. 2.2 stage recursion, transposed) and of RKCK
  * (Sec. 2.1 stage equations with the Table 1 coefficients, transposed).
@@ -335,12 +360,16 @@ size_t rk_batch_workspace_bytes(rk_batch b, const int64_t *n_sys, int64_t n_tota
  *   g[k]                [2][n_sys[k]] device (T, rho)
  *   status[k], stats[k] device [n_sys[k]] / [RK_NSTATS][n_sys[k]], or a NULL
  *                       array; values of the last substep
+ *   carry[k]            device [rk_carry_rows(problem k)][n_sys[k]] controller state
+ *                       carried from substep to substep and from call to call (see
+ *                       rk_integrate_rkc_carry), or a NULL array: every substep a restart
  *   slot_map, n_total   interleaved form only (else NULL, 0)
  *   ws, ws_bytes        at least rk_batch_workspace_bytes(...), 256-byte aligned
  * Asynchronous on `stream`.  Calls on one batch must not overlap. */
 int rk_batch_integrate_rkc(rk_batch b, const int64_t *n_sys, double *const *y,
                            const double *const *g, int32_t *const *status,
-                           int32_t *const *stats, const int32_t *slot_map, int64_t n_total,
+                           int32_t *const *stats, double *const *carry,
+                           const int32_t *slot_map, int64_t n_total,
                            double t0, double dt, int32_t n_substeps, double rtol, double atol,
                            const rk_options *opt, const rk_batch_schedule *sched, void *ws,
                            size_t ws_bytes, void *stream);

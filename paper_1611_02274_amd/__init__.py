@@ -105,7 +105,7 @@ def _check_tensor(x, name, rows, n, dtype):
 
 
 def _integrate(method, problem: Problem, y0, g, t0, t1, rtol, atol, out=None, status=None,
-               stats=None, stream=None, **opts):
+               stats=None, stream=None, carry=None, **opts):
     import torch
     if y0.dim() != 2:
         raise ValueError("y0 must be [N, n]")
@@ -132,11 +132,20 @@ def _integrate(method, problem: Problem, y0, g, t0, t1, rtol, atol, out=None, st
         s = stream if stream is not None else torch.cuda.current_stream(dev)
         nws = L.rk_workspace_bytes(problem.handle, method, n, optp)
         ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev) if nws else None
-        fn = L.rk_integrate_rkck if method == RK_METHOD_RKCK else L.rk_integrate_rkc
-        _lib.check(fn(problem.handle, n, y0.data_ptr(), out.data_ptr(),
-                      g.data_ptr() if problem.n_param else None, float(t0), float(t1),
-                      float(rtol), float(atol), status.data_ptr(), stats.data_ptr(),
-                      ws.data_ptr() if ws is not None else None, nws, optp, s.cuda_stream))
+        gp = g.data_ptr() if problem.n_param else None
+        wp = ws.data_ptr() if ws is not None else None
+        if carry is None:
+            fn = L.rk_integrate_rkck if method == RK_METHOD_RKCK else L.rk_integrate_rkc
+            _lib.check(fn(problem.handle, n, y0.data_ptr(), out.data_ptr(), gp, float(t0),
+                          float(t1), float(rtol), float(atol), status.data_ptr(),
+                          stats.data_ptr(), wp, nws, optp, s.cuda_stream))
+        else:
+            _check_tensor(carry, "carry", carry_rows(problem), n, torch.float64)
+            fn = (L.rk_integrate_rkck_carry if method == RK_METHOD_RKCK
+                  else L.rk_integrate_rkc_carry)
+            _lib.check(fn(problem.handle, n, y0.data_ptr(), out.data_ptr(), gp, float(t0),
+                          float(t1), float(rtol), float(atol), status.data_ptr(),
+                          stats.data_ptr(), carry.data_ptr(), wp, nws, optp, s.cuda_stream))
     return out, status, stats
 
 
@@ -146,8 +155,15 @@ def integrate_rkck(problem, y0, g, t0, t1, rtol, atol, **kw):
 
 
 def integrate_rkc(problem, y0, g, t0, t1, rtol, atol, **kw):
-    """RKC integration (Sec. 2.2, Sec. 3.2, Appendix).  Returns (y1, status, stats)."""
+    """RKC integration (Sec. 2.2, Sec. 3.2, Appendix).  Returns (y1, status, stats).
+    carry=tensor [carry_rows(problem), n]: the controller state carried between
+    calls instead of the restart (zeros at first; updated in place)."""
     return _integrate(RK_METHOD_RKC, problem, y0, g, t0, t1, rtol, atol, **kw)
+
+
+def carry_rows(problem) -> int:
+    """Rows of a carried-state array for `problem` (7 + N)."""
+    return int(_lib.lib().rk_carry_rows(problem.handle))
 
 
 class Tape:
@@ -406,9 +422,12 @@ class Batch:
 
     def integrate_rkc(self, ys, gs, t0, dt, n_substeps, rtol, atol, mode="persistent",
                       waves_per_cu=0, order=None, refill=None, use_graph=False, slot_map=None,
-                      status=None, stats=None, stream=None, max_steps=None):
+                      status=None, stats=None, stream=None, max_steps=None, carry=None):
         """ys[k] [N_k, n_k] and gs[k] [2, n_k] float64 CUDA tensors per problem,
-        integrated in place; status / stats: lists of tensors or None."""
+        integrated in place; status / stats: lists of tensors or None; carry: a
+        list of [carry_rows(problem k), n_k] float64 tensors carrying the
+        controller state from substep to substep (zeros at first), or None for
+        a restart at every substep."""
         import torch
         m = len(self.problems)
         if len(ys) != m or len(gs) != m:
@@ -417,6 +436,8 @@ class Batch:
         for k, (p, y, g) in enumerate(zip(self.problems, ys, gs)):
             _check_tensor(y, f"ys[{k}]", p.n_eq, n[k], torch.float64)
             _check_tensor(g, f"gs[{k}]", p.n_param, n[k], torch.float64)
+            if carry is not None:
+                _check_tensor(carry[k], f"carry[{k}]", carry_rows(p), n[k], torch.float64)
         dev = ys[0].device
         sched = self.schedule(mode, waves_per_cu, order, refill, use_graph)
         n_total = sum(n) if mode == "interleaved" else 0
@@ -439,7 +460,7 @@ class Batch:
                 # one workspace per batch, reused: a captured graph refers to it
                 ws = self._ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
             _lib.check(L.rk_batch_integrate_rkc(
-                self._h, nn, ptrs(ys), ptrs(gs), ptrs(status), ptrs(stats),
+                self._h, nn, ptrs(ys), ptrs(gs), ptrs(status), ptrs(stats), ptrs(carry),
                 slot_map.data_ptr() if mode == "interleaved" else None, n_total, float(t0),
                 float(dt), int(n_substeps), float(rtol), float(atol),
                 C.byref(opt) if opt is not None else None, C.byref(sched), ws.data_ptr(), nws,

@@ -83,6 +83,13 @@ def lib():
                                              C.c_double, C.c_double, vp, vp, vp, C.c_size_t,
                                              i64, C.c_int32, C.POINTER(Options), vp]
         L.rk_integrate_rkc_taped.restype = C.c_int
+        L.rk_carry_rows.argtypes = [vp]
+        L.rk_carry_rows.restype = C.c_size_t
+        for name in ("rk_integrate_rkck_carry", "rk_integrate_rkc_carry"):
+            getattr(L, name).argtypes = [vp, i64, dp, dp, dp, C.c_double, C.c_double,
+                                         C.c_double, C.c_double, vp, vp, dp, vp, C.c_size_t,
+                                         C.POINTER(Options), vp]
+            getattr(L, name).restype = C.c_int
         L.rk_integrate_rkck_taped.argtypes = L.rk_integrate_rkc_taped.argtypes
         L.rk_integrate_rkck_taped.restype = C.c_int
         L.rk_adjoint_rkck_workspace_bytes.argtypes = [vp, i64, C.c_int32]
@@ -102,7 +109,8 @@ def lib():
         L.rk_batch_workspace_bytes.argtypes = [vp, C.POINTER(i64), i64, C.POINTER(BatchSchedule)]
         L.rk_batch_workspace_bytes.restype = C.c_size_t
         L.rk_batch_integrate_rkc.argtypes = [vp, C.POINTER(i64), C.POINTER(vp), C.POINTER(vp),
-                                             C.POINTER(vp), C.POINTER(vp), vp, i64, C.c_double,
+                                             C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
+                                             i64, C.c_double,
                                              C.c_double, C.c_int32, C.c_double, C.c_double,
                                              C.POINTER(Options), C.POINTER(BatchSchedule),
                                              vp, C.c_size_t, vp]

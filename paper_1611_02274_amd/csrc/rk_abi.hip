@@ -165,12 +165,14 @@ void fill_args(rkmi::LaunchArgs& a, int method, int64_t n, const double* y0, dou
   a.ws_bytes = ws_bytes;
   a.order = nullptr;
   a.pilot = 0;
+  a.carry = nullptr;
 }
 
 int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1, const double* g,
               double t0, double t1, double rtol, double atol, int32_t* status, int32_t* stats,
               void* ws, size_t ws_bytes, const rk_options* opt, void* stream,
-              const rkmi::TapeArgs* tape = nullptr) {
+              const rkmi::TapeArgs* tape = nullptr, double* carry = nullptr,
+              bool want_carry = false) {
   g_err.clear();
   if (!p) return fail(RK_EINVAL, "problem handle is NULL");
   if (tape && !p->taped)
@@ -199,6 +201,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if ((rc = check_device_ptr(status, 4, "status", true))) return rc;
   if ((rc = check_device_ptr(stats, 4, "stats", true))) return rc;
   if ((rc = check_device_ptr(ws, 8, "ws", true))) return rc;
+  if (want_carry && (rc = check_device_ptr(carry, 8, "carry", false))) return rc;
   if (tape) {
     if ((rc = check_device_ptr(tape->tape, 256, "tape", false))) return rc;
     const size_t need = rkmi::tape_layout(n, tape->cap, tape->K, p->n_eq).bytes;
@@ -207,7 +210,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
                   need);
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  if (t1 == t0 && !tape) {
+  if (t1 == t0 && !tape && !carry) {
     // nothing to integrate: copy the state, zero status and statistics (a
     // kernel rather than memset/memcpy nodes, so the call is graph-capturable)
     const int64_t blocks = (n + 255) / 256;
@@ -218,6 +221,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   }
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
+  a.carry = carry;
   if ((rc = problem_device_data(p, &a.prm))) return rc;
   if (opt && opt->cost_order) {
     const int64_t base = p->workspace(method, a.schedule, n);
@@ -419,6 +423,27 @@ int rk_integrate_rkc_taped(rk_problem p, int64_t n_sys, const double* y0, double
   const rkmi::TapeArgs t{tape, tape_bytes, max_accepted, ckpt_every};
   return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats,
                    nullptr, 0, opt, stream, &t);
+}
+
+size_t rk_carry_rows(rk_problem p) {
+  g_err.clear();
+  return p ? (size_t)(rkmi::kCarryRows + p->n_eq) : 0;
+}
+
+int rk_integrate_rkck_carry(rk_problem p, int64_t n_sys, const double* y0, double* y1,
+                            const double* g, double t0, double t1, double rtol, double atol,
+                            int32_t* status, int32_t* stats, double* carry, void* ws,
+                            size_t ws_bytes, const rk_options* opt, void* stream) {
+  return integrate(rkmi::kMethodRkck, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats, ws,
+                   ws_bytes, opt, stream, nullptr, carry, true);
+}
+
+int rk_integrate_rkc_carry(rk_problem p, int64_t n_sys, const double* y0, double* y1,
+                           const double* g, double t0, double t1, double rtol, double atol,
+                           int32_t* status, int32_t* stats, double* carry, void* ws,
+                           size_t ws_bytes, const rk_options* opt, void* stream) {
+  return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats, ws,
+                   ws_bytes, opt, stream, nullptr, carry, true);
 }
 
 int rk_integrate_rkck_taped(rk_problem p, int64_t n_sys, const double* y0, double* y1,
@@ -687,10 +712,10 @@ size_t rk_batch_workspace_bytes(rk_batch b, const int64_t* n_sys, int64_t n_tota
 
 int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
                            const double* const* g, int32_t* const* status, int32_t* const* stats,
-                           const int32_t* slot_map, int64_t n_total, double t0, double dt,
-                           int32_t n_substeps, double rtol, double atol, const rk_options* opt,
-                           const rk_batch_schedule* sched, void* ws, size_t ws_bytes,
-                           void* stream) {
+                           double* const* carry, const int32_t* slot_map, int64_t n_total,
+                           double t0, double dt, int32_t n_substeps, double rtol, double atol,
+                           const rk_options* opt, const rk_batch_schedule* sched, void* ws,
+                           size_t ws_bytes, void* stream) {
   g_err.clear();
   if (!b) return fail(RK_EINVAL, "batch handle is NULL");
   if (!n_sys || !y || !g) return fail(RK_EINVAL, "n_sys, y and g are required");
@@ -704,6 +729,12 @@ int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
   int rc = batch_args(b, n_sys, y, g, status, stats, slot_map, n_total, t0, dt, n_substeps, rtol,
                       atol, opt, sched, ws, ws_bytes, true, a);
   if (rc) return rc;
+  if (carry)
+    for (int k = 0; k < b->n; ++k) {
+      if (n_sys[k] == 0) continue;
+      if ((rc = check_device_ptr(carry[k], 8, "carry", false))) return rc;
+      a.net[b->user_to_entry[k]].carry = carry[k];
+    }
   if ((rc = check_device_ptr(ws, 256, "ws", true))) return rc;
   std::lock_guard<std::mutex> lock(b->mu);
   rc = b->entry->launch(&a, stream);
@@ -730,6 +761,25 @@ int rkmi_test_host_integrate(int32_t method, rk_problem p, int64_t n, const doub
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0, &o);
   a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
+  return p->host(&a);
+}
+
+// As rkmi_test_host_integrate with a carried controller state (host array
+// [kCarryRows + N][n], read and rewritten).
+int rkmi_test_host_integrate_carry(int32_t method, rk_problem p, int64_t n, const double* y0,
+                                   double* y1, const double* g, double t0, double t1,
+                                   double rtol, double atol, int32_t* status, int32_t* stats,
+                                   int64_t max_steps, double* carry) {
+  g_err.clear();
+  if (!p || !p->host || n < 0 || !y0 || !y1 || (p->n_param && !g) || !(t1 >= t0) ||
+      !(rtol > 0.0) || !(atol >= 0.0) || !carry)
+    return fail(RK_EINVAL, "invalid arguments");
+  rk_options o{};
+  o.max_steps = max_steps;
+  rkmi::LaunchArgs a;
+  fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0, &o);
+  a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
+  a.carry = carry;
   return p->host(&a);
 }
 

@@ -35,6 +35,7 @@ struct BatchNet {
   const double* g;     // [2][n]
   int32_t* status;     // [n] or null
   int32_t* stats;      // [kNStats][n] or null
+  double* carry;       // [kCarryRows + N][n] or null
 };
 
 struct BatchParams {
@@ -101,11 +102,11 @@ __device__ void batch_run_net(const BatchNet& d, Ctl c, int refill, unsigned lon
   c.refill = refill;
   if constexpr (Prob::kGroupLanes > 1) {
     group_persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats,
-                                            queue, lds, nullptr);
+                                            queue, lds, nullptr, d.carry);
   } else {
     double* slot = Prob::kColumns ? colbase + threadIdx.x : lds + threadIdx.x;
     persistent_loop<Prob, kMethodRkc>(d.prm, d.n, d.y, d.y, d.g, c, d.status, d.stats, queue,
-                                      slot, nullptr);
+                                      slot, nullptr, d.carry);
   }
 }
 
@@ -133,7 +134,7 @@ __global__ void batch_queue_reset(unsigned long long* queues, int n_net) {
 template <class Prob>
 __device__ void batch_plain_one(const BatchNet& d, const Ctl& c, int64_t local, double* slot) {
   integrate_system<Prob, kMethodRkc>(d.prm, d.n, local, d.y, d.y, d.g, c, d.status, d.stats,
-                                     slot);
+                                     slot, d.carry);
 }
 
 template <class... P>
@@ -209,7 +210,7 @@ BatchParams batch_params(const BatchArgs* a) {
   BatchParams bp{};
   for (int k = 0; k < kMaxBatchNets; ++k) {
     bp.net[k] = BatchNet{a->net[k].prm, a->net[k].n, a->net[k].y, a->net[k].g, a->net[k].status,
-                         a->net[k].stats};
+                         a->net[k].stats, a->net[k].carry};
     bp.order[k] = a->order[k];
     bp.map_net[k] = a->map_net[k];
     bp.refill[k] = a->refill[k] > 0 ? (a->refill[k] > kLdsStride ? kLdsStride : a->refill[k])
@@ -264,6 +265,7 @@ int batch_enqueue(const BatchArgs* a, hipStream_t s) {
         substep_interval(a, st, la.ctl);
         la.status = a->net[k].status;
         la.stats = a->net[k].stats;
+        la.carry = a->net[k].carry;
         la.ws = a->ws;
         la.ws_bytes = a->ws_bytes;
         if (rc == kLaunchOk && la.n > 0) rc = launch_method<Prob, kMethodRkc, false>(&la, s);

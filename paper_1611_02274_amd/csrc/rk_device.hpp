@@ -100,6 +100,17 @@ struct WavesPerEu<P, std::void_t<decltype(P::kWavesPerEu)>> {
   static constexpr int value = P::kWavesPerEu;
 };
 
+// Controller state carried from one call to the next instead of the restart
+// (Sec. 3 mentions the alternative): rows of a [kCarryRows + N][n] array, the
+// RKC eigenvector estimate in the last N rows; RKCK uses kCarryValid and
+// kCarryH.  kCarryValid = 0 asks for the restart; a call leaves 1 when its
+// system ended OK.  The carried next step is the one the controller wanted
+// before the final step was cut to the interval end.
+enum : int {
+  kCarryValid = 0, kCarryH, kCarryHPrev, kCarryErrPrev, kCarrySigma, kCarryNstep,
+  kCarryHavePrev, kCarryRows
+};
+
 // A vector of N unknowns held in registers.
 template <int N>
 struct RegVec {
@@ -300,6 +311,8 @@ struct RkckState {
   int64_t attempts;
   int32_t n_acc, n_rej, n_rhs, status;
   bool fvalid;
+  double h_want;   // the step before the cut to the interval end
+  bool cut;        // the last accepted step was cut
 };
 
 // Points the state's vectors at their slot columns (column storage only).
@@ -318,6 +331,8 @@ template <class Prob>
 RKMI_HD void rkck_begin(RkckState<Prob>& S, const Ctl& c) {
   S.t = c.t0;
   S.h = 0.5 * c.hmax;
+  S.h_want = S.h;
+  S.cut = false;
   S.fvalid = false;
   S.status = kSysOk;
   S.attempts = 0;
@@ -334,6 +349,7 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
     S.status = kSysMaxSteps;
     return false;
   }
+  S.h_want = S.h;
   S.h = fmin(c.t1 - S.t, S.h);
   if (!S.fvalid) {
     eval_rhs<Prob>(L, prm, S.y, S.F);
@@ -364,6 +380,7 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
       return false;
     }
   } else {
+    S.cut = S.h < S.h_want;
     S.t += S.h;
     const double hacc = S.h;
     const double hn = (err > kErrCon) ? kSafety * S.h * crm::cr_pow(err, kPGrow) : S.h * 5.0;
@@ -571,6 +588,8 @@ struct RkcState {
   int64_t nstep, attempts;
   int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
   bool first, have_prev;
+  double h_want;   // the step before the cut to the interval end
+  bool cut;        // the last accepted step was cut
 };
 
 template <class Prob>
@@ -604,6 +623,8 @@ RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params
 #pragma unroll U
   for (int i = 0; i < N; ++i) vslot[i * kLdsStride] = S.Fn[i];
   S.h = S.h_prev = S.err_prev = S.sigma = S.cbrt_err_prev = 0.0;
+  S.h_want = 0.0;
+  S.cut = false;
   S.nstep = 0;
   S.first = true;
   S.have_prev = false;
@@ -620,6 +641,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     S.status = kSysMaxSteps;
     return false;
   }
+  S.h_want = S.h;
   if (1.1 * S.h >= fabs(c.t1 - S.t)) S.h = fabs(c.t1 - S.t);
   if (S.nstep % c.sr_period == 0) {
     int it;
@@ -679,6 +701,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
       return false;
     }
   } else {
+    S.cut = S.h < S.h_want;
     S.t += S.h;
     ++S.nstep;
     ++S.n_acc;
@@ -737,21 +760,31 @@ struct Driver<Prob, kMethodRkck, Rec> {
   RKMI_HD const Vec<Prob>& state() const { return S.y; }
   RKMI_HD int64_t accepted() const { return S.n_acc; }
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
-                     const double* y0, const double* g, double* slot) {
+                     const double* y0, const double* g, double* slot,
+                     const double* carry = nullptr) {
     Prob::init(L, prm, g, i, n, slot);
     rkck_bind<Prob>(S, slot);
 #pragma unroll U
     for (int k = 0; k < N; ++k) S.y[k] = y0[(int64_t)k * n + i];
     rkck_begin<Prob>(S, c);
+    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) {
+      S.h = carry[(int64_t)kCarryH * n + i];
+      S.h_want = S.h;
+    }
     return S.t < c.t1;
   }
   RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
     return rkck_attempt<Prob, Rec>(L, prm, c, S, slot, rec);
   }
-  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
+                      double* carry = nullptr, const double* = nullptr) const {
     if (y1)
 #pragma unroll U
       for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.y[k];
+    if (carry) {
+      carry[(int64_t)kCarryValid * n + i] = S.status == kSysOk ? 1.0 : 0.0;
+      carry[(int64_t)kCarryH * n + i] = S.cut ? S.h_want : S.h;
+    }
     int32_t st[kNStats];
     rkck_stats(S, st);
     if (status) status[i] = S.status;
@@ -770,21 +803,49 @@ struct Driver<Prob, kMethodRkc, Rec> {
   RKMI_HD const Vec<Prob>& state() const { return S.yn; }
   RKMI_HD int64_t accepted() const { return S.nstep; }
   RKMI_HD bool start(const typename Prob::Params& prm, const Ctl& c, int64_t n, int64_t i,
-                     const double* y0, const double* g, double* slot) {
+                     const double* y0, const double* g, double* slot,
+                     const double* carry = nullptr) {
     Prob::init(L, prm, g, i, n, slot);
     rkc_bind<Prob>(S, slot);
 #pragma unroll U
     for (int k = 0; k < N; ++k) S.yn[k] = y0[(int64_t)k * n + i];
     rkc_begin<Prob>(L, prm, c, S, slot);
+    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) {
+      S.h = carry[(int64_t)kCarryH * n + i];
+      S.h_prev = carry[(int64_t)kCarryHPrev * n + i];
+      S.err_prev = carry[(int64_t)kCarryErrPrev * n + i];
+      S.sigma = carry[(int64_t)kCarrySigma * n + i];
+      S.nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
+      S.have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
+      // err_prev^(1/3), as the controller formed it when err_prev was accepted
+      S.cbrt_err_prev = S.have_prev ? crm::cr_pow(S.err_prev, 1.0 / 3.0) : 0.0;
+      S.first = false;
+      double* const vslot = col_ptr<Prob>(slot, kCV);
+#pragma unroll U
+      for (int k = 0; k < N; ++k) vslot[k * kLdsStride] = carry[(int64_t)(kCarryRows + k) * n + i];
+    }
     return S.t < c.t1;
   }
   RKMI_HD bool attempt(const typename Prob::Params& prm, const Ctl& c, double* slot) {
     return rkc_attempt<Prob, Rec>(L, prm, c, S, slot, rec);
   }
-  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats) const {
+  RKMI_HD void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
+                      double* carry = nullptr, const double* slot = nullptr) const {
     if (y1)
 #pragma unroll U
       for (int k = 0; k < N; ++k) y1[(int64_t)k * n + i] = S.yn[k];
+    if (carry) {
+      carry[(int64_t)kCarryValid * n + i] = S.status == kSysOk ? 1.0 : 0.0;
+      carry[(int64_t)kCarryH * n + i] = S.cut ? S.h_want : S.h;
+      carry[(int64_t)kCarryHPrev * n + i] = S.h_prev;
+      carry[(int64_t)kCarryErrPrev * n + i] = S.err_prev;
+      carry[(int64_t)kCarrySigma * n + i] = S.sigma;
+      carry[(int64_t)kCarryNstep * n + i] = (double)S.nstep;
+      carry[(int64_t)kCarryHavePrev * n + i] = S.have_prev ? 1.0 : 0.0;
+      const double* const vslot = slot + (Prob::kLaneDoubles) * kLdsStride;
+#pragma unroll U
+      for (int k = 0; k < N; ++k) carry[(int64_t)(kCarryRows + k) * n + i] = vslot[k * kLdsStride];
+    }
     int32_t st[kNStats];
     rkc_stats(S, st);
     if (status) status[i] = S.status;
@@ -798,12 +859,13 @@ struct Driver<Prob, kMethodRkc, Rec> {
 template <class Prob, int Method>
 RKMI_HD void integrate_system(const typename Prob::Params& prm, int64_t n, int64_t i,
                               const double* y0, double* y1, const double* g, const Ctl& c,
-                              int32_t* status, int32_t* stats, double* slot) {
+                              int32_t* status, int32_t* stats, double* slot,
+                              double* carry = nullptr) {
   Driver<Prob, Method> D;
-  if (D.start(prm, c, n, i, y0, g, slot))
+  if (D.start(prm, c, n, i, y0, g, slot, carry))
     while (D.attempt(prm, c, slot)) {
     }
-  D.finish(n, i, y1, status, stats);
+  D.finish(n, i, y1, status, stats, carry, slot);
 }
 
 // =========================================================================
@@ -837,13 +899,14 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void plain_kernel(
                                                            int32_t* __restrict__ status,
                                                            int32_t* __restrict__ stats,
                                                            double* cols,
-                                                           const int32_t* __restrict__ order) {
+                                                           const int32_t* __restrict__ order,
+                                                           double* __restrict__ carry) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   const int64_t q = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (q >= n) return;
   const int64_t i = order ? (int64_t)order[q] : q;
   integrate_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats,
-                                 lane_slot<Prob, Method>(lds, cols));
+                                 lane_slot<Prob, Method>(lds, cols), carry);
 }
 
 // Persistent loop of one wave over the systems of one queue: finished lanes
@@ -861,7 +924,7 @@ template <class Prob, int Method>
 __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, const double* y0,
                                 double* y1, const double* g, const Ctl& c, int32_t* status,
                                 int32_t* stats, unsigned long long* queue, double* slot,
-                                const int32_t* order) {
+                                const int32_t* order, double* carry) {
   const int lane = threadIdx.x;
   Driver<Prob, Method> D;
   int64_t i = -1;
@@ -883,8 +946,8 @@ __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, con
         const unsigned long long idx = base + (unsigned long long)__popcll(below);
         if (idx < (unsigned long long)n) {
           i = order ? (int64_t)order[idx] : (int64_t)idx;
-          active = D.start(prm, c, n, i, y0, g, slot);
-          if (!active) D.finish(n, i, y1, status, stats);
+          active = D.start(prm, c, n, i, y0, g, slot, carry);
+          if (!active) D.finish(n, i, y1, status, stats, carry, slot);
         } else {
           retired = true;
         }
@@ -892,7 +955,7 @@ __device__ void persistent_loop(const typename Prob::Params& prm, int64_t n, con
     }
     if (!__ballot(!retired)) break;
     if (active && !D.attempt(prm, c, slot)) {
-      D.finish(n, i, y1, status, stats);
+      D.finish(n, i, y1, status, stats, carry, slot);
       active = false;
     }
   }
@@ -911,10 +974,11 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void persistent_ke
                                                                 int32_t* __restrict__ stats,
                                                                 unsigned long long* queue,
                                                                 double* cols,
-                                                                const int32_t* __restrict__ order) {
+                                                                const int32_t* __restrict__ order,
+                                                                double* __restrict__ carry) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
   persistent_loop<Prob, Method>(prm, n, y0, y1, g, c, status, stats, queue,
-                                lane_slot<Prob, Method>(lds, cols), order);
+                                lane_slot<Prob, Method>(lds, cols), order, carry);
 }
 
 }  // namespace rkmi

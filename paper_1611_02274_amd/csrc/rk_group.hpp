@@ -170,14 +170,16 @@ struct GRkck {
   static constexpr int S = GP::S;
   typename GP::Lane L;
   double y[S], F[S];
-  double t, h;
+  double t, h, h_want;
   int64_t attempts;
   int32_t n_acc, n_rej, n_rhs, status;
-  bool fvalid;
+  bool fvalid, cut;
 
   __device__ void begin(const Ctl& c) {
     t = c.t0;
     h = 0.5 * c.hmax;
+    h_want = h;
+    cut = false;
     fvalid = false;
     status = kSysOk;
     attempts = 0;
@@ -189,6 +191,7 @@ struct GRkck {
       status = kSysMaxSteps;
       return false;
     }
+    h_want = h;
     h = fmin(c.t1 - t, h);
     if (!fvalid) {
       group_rhs<GP>(L, x, y, F);
@@ -257,6 +260,7 @@ struct GRkck {
         return false;
       }
     } else {
+      cut = h < h_want;
       t += h;
       const double hn = (err > kErrCon) ? kSafety * h * crm::cr_pow(err, kPGrow) : h * 5.0;
       h = fmax(kRkckHmin, fmin(c.hmax, hn));
@@ -281,6 +285,16 @@ struct GRkck {
   }
   __device__ const double (&state() const)[S] { return y; }
   __device__ double (&state())[S] { return y; }
+  // carried controller state (rows of the carry array), as the one-lane driver
+  __device__ void load_carry(const Grp<GP>&, const double* carry, int64_t n, int64_t i) {
+    h = carry[(int64_t)kCarryH * n + i];
+    h_want = h;
+  }
+  __device__ void store_carry(const Grp<GP>& x, double* carry, int64_t n, int64_t i) const {
+    if (x.r != 0) return;
+    carry[(int64_t)kCarryValid * n + i] = status == kSysOk ? 1.0 : 0.0;
+    carry[(int64_t)kCarryH * n + i] = cut ? h_want : h;
+  }
 };
 
 // -------------------------------------------------------------------- RKC
@@ -289,10 +303,10 @@ struct GRkc {
   static constexpr int S = GP::S, N = GP::N;
   typename GP::Lane L;
   double yn[S], Fn[S], v[S];
-  double t, h, h_prev, err_prev, sigma, cbrt_err_prev;
+  double t, h, h_prev, err_prev, sigma, cbrt_err_prev, h_want;
   int64_t nstep, attempts;
   int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
-  bool first, have_prev;
+  bool first, have_prev, cut;
 
   __device__ void begin(const Grp<GP>& x, const Ctl& c) {
     t = c.t0;
@@ -307,10 +321,11 @@ struct GRkc {
       for (int i = 0; i < S; ++i) Fn[i] = 0.0;
     }
     gcopy<GP>(v, Fn);
-    h = h_prev = err_prev = sigma = cbrt_err_prev = 0.0;
+    h = h_prev = err_prev = sigma = cbrt_err_prev = h_want = 0.0;
     nstep = 0;
     first = true;
     have_prev = false;
+    cut = false;
   }
 
   // Nonlinear power method (Appendix), as spec_rad.
@@ -430,6 +445,7 @@ struct GRkc {
       status = kSysMaxSteps;
       return false;
     }
+    h_want = h;
     if (1.1 * h >= fabs(c.t1 - t)) h = fabs(c.t1 - t);
     if (nstep % c.sr_period == 0) {
       int it;
@@ -487,6 +503,7 @@ struct GRkc {
         return false;
       }
     } else {
+      cut = h < h_want;
       t += h;
       ++nstep;
       ++n_acc;
@@ -526,6 +543,36 @@ struct GRkc {
   }
   __device__ const double (&state() const)[S] { return yn; }
   __device__ double (&state())[S] { return yn; }
+  __device__ void load_carry(const Grp<GP>& x, const double* carry, int64_t n, int64_t i) {
+    h = carry[(int64_t)kCarryH * n + i];
+    h_prev = carry[(int64_t)kCarryHPrev * n + i];
+    err_prev = carry[(int64_t)kCarryErrPrev * n + i];
+    sigma = carry[(int64_t)kCarrySigma * n + i];
+    nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
+    have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
+    cbrt_err_prev = have_prev ? crm::cr_pow(err_prev, 1.0 / 3.0) : 0.0;
+    first = false;
+#pragma unroll
+    for (int m = 0; m < S; ++m) {
+      const int k = x.sp[m];
+      v[m] = k >= 0 ? carry[(int64_t)(kCarryRows + k) * n + i] : 0.0;
+    }
+  }
+  __device__ void store_carry(const Grp<GP>& x, double* carry, int64_t n, int64_t i) const {
+#pragma unroll
+    for (int m = 0; m < S; ++m) {
+      const int k = x.sp[m];
+      if (k >= 0) carry[(int64_t)(kCarryRows + k) * n + i] = v[m];
+    }
+    if (x.r != 0) return;
+    carry[(int64_t)kCarryValid * n + i] = status == kSysOk ? 1.0 : 0.0;
+    carry[(int64_t)kCarryH * n + i] = cut ? h_want : h;
+    carry[(int64_t)kCarryHPrev * n + i] = h_prev;
+    carry[(int64_t)kCarryErrPrev * n + i] = err_prev;
+    carry[(int64_t)kCarrySigma * n + i] = sigma;
+    carry[(int64_t)kCarryNstep * n + i] = (double)nstep;
+    carry[(int64_t)kCarryHavePrev * n + i] = have_prev ? 1.0 : 0.0;
+  }
 };
 
 template <class GP, int Method>
@@ -536,7 +583,8 @@ template <class GP, int Method>
 struct GDriver {
   GDriverState<GP, Method> D;
   __device__ bool start(const typename GP::Params& prm, const Ctl& c, int64_t n, int64_t i,
-                        const double* y0, const double* g, const Grp<GP>& x) {
+                        const double* y0, const double* g, const Grp<GP>& x,
+                        const double* carry = nullptr) {
     GP::init(D.L, prm, g, i, n, x);
     auto& y = D.state();
 #pragma unroll
@@ -548,12 +596,14 @@ struct GDriver {
       D.begin(c);
     else
       D.begin(x, c);
+    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) D.load_carry(x, carry, n, i);
     return D.t < c.t1;
   }
   __device__ bool attempt(const Ctl& c, const Grp<GP>& x) { return D.attempt(x, c); }
   __device__ void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
-                         const Grp<GP>& x) const {
+                         const Grp<GP>& x, double* carry = nullptr) const {
     const auto& y = D.state();
+    if (carry) D.store_carry(x, carry, n, i);
     if (y1)
 #pragma unroll
       for (int m = 0; m < GP::S; ++m) {
@@ -601,7 +651,7 @@ template <class GP, int Method>
 __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n, const double* y0,
                                       double* y1, const double* g, const Ctl& c, int32_t* status,
                                       int32_t* stats, unsigned long long* queue, double* lds,
-                                      const int32_t* order) {
+                                      const int32_t* order, double* carry) {
   const int lane = threadIdx.x;
   const Grp<GP> x = group_of<GP>(lds);
   const int first_lane = lane - x.r;
@@ -626,8 +676,8 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
         const unsigned long long idx = base + (unsigned long long)(__popcll(below) / GP::kL);
         if (idx < (unsigned long long)n) {
           i = order ? (int64_t)order[idx] : (int64_t)idx;
-          active = D.start(prm, c, n, i, y0, g, x);
-          if (!active) D.finish(n, i, y1, status, stats, x);
+          active = D.start(prm, c, n, i, y0, g, x, carry);
+          if (!active) D.finish(n, i, y1, status, stats, x, carry);
         } else {
           retired = true;
         }
@@ -635,7 +685,7 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
     }
     if (!__ballot(!retired)) break;
     if (active && !D.attempt(c, x)) {
-      D.finish(n, i, y1, status, stats, x);
+      D.finish(n, i, y1, status, stats, x, carry);
       active = false;
     }
   }
@@ -645,9 +695,11 @@ template <class GP, int Method, bool kPilot = false>
 __global__ __launch_bounds__(kLdsStride) void group_persistent_kernel(
     typename GP::Params prm, int64_t n, const double* y0, double* y1,
     const double* __restrict__ g, Ctl c, int32_t* __restrict__ status,
-    int32_t* __restrict__ stats, unsigned long long* queue, const int32_t* __restrict__ order) {
+    int32_t* __restrict__ stats, unsigned long long* queue, const int32_t* __restrict__ order,
+    double* __restrict__ carry) {
   __shared__ double lds[group_lds_doubles<GP>()];
-  group_persistent_loop<GP, Method>(prm, n, y0, y1, g, c, status, stats, queue, lds, order);
+  group_persistent_loop<GP, Method>(prm, n, y0, y1, g, c, status, stats, queue, lds, order,
+                                    carry);
 }
 
 template <class GP, int Method, bool kPilot>
@@ -667,7 +719,7 @@ int launch_group_method(const LaunchArgs* a, hipStream_t s) {
   unsigned long long* queue = static_cast<unsigned long long*>(a->ws);
   queue_reset_kernel<><<<1, 1, 0, s>>>(queue);
   group_persistent_kernel<GP, Method, kPilot><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
-      a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, a->order);
+      a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, a->order, a->carry);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 

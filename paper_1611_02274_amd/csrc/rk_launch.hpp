@@ -82,7 +82,7 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
   if (!persistent) {
     if (col_bytes && ws_bytes < kQueueBytes + (size_t)blocks * col_bytes) return kLaunchWorkspace;
     plain_kernel<Prob, Method, kPilot><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
-        prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, cols, a->order);
+        prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, cols, a->order, a->carry);
     return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
   }
   int64_t grid = 0;
@@ -96,7 +96,8 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
   unsigned long long* queue = reinterpret_cast<unsigned long long*>(ws);
   queue_reset_kernel<><<<1, 1, 0, s>>>(queue);
   persistent_kernel<Prob, Method, kPilot><<<dim3((unsigned)grid), dim3(kLdsStride), 0, s>>>(
-      prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, cols, a->order);
+      prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, queue, cols, a->order,
+      a->carry);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
@@ -130,10 +131,10 @@ int host_run(const LaunchArgs* a) {
   for (int64_t i = 0; i < a->n; ++i) {
     if (a->method == kMethodRkck)
       integrate_system<Prob, kMethodRkck>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
-                                          a->stats, slot.data());
+                                          a->stats, slot.data(), a->carry);
     else
       integrate_system<Prob, kMethodRkc>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
-                                         a->stats, slot.data());
+                                         a->stats, slot.data(), a->carry);
   }
   return 0;
 }

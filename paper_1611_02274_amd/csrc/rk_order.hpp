@@ -33,9 +33,13 @@ constexpr int kOrderBuckets = 4096;
 constexpr int kOrderScanThreads = 256;
 constexpr int kOrderPerThread = kOrderBuckets / kOrderScanThreads;
 // The pilot runs at rtol * kPilotLoosen (atol scaled alike), at most
-// kPilotRtolMax (and never tighter than the integration itself).
+// kPilotRtolMax (and never tighter than the integration itself), and stops a
+// system after kPilotMaxAttempts attempts: the costliest systems then share
+// the top bucket (they start first either way), and no wave of the pilot
+// waits long for one slow system.
 constexpr double kPilotLoosen = 1.0e4;
 constexpr double kPilotRtolMax = 1.0e-3;
+constexpr int64_t kPilotMaxAttempts = 192;
 
 constexpr size_t order_align(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -66,6 +70,7 @@ inline Ctl pilot_ctl(const Ctl& c) {
   p.atol = c.atol * f;
   const int mmax = (int)round(sqrt(r / (10.0 * kUround)));
   p.mmax = mmax < 2 ? 2 : mmax;
+  if (p.max_steps > kPilotMaxAttempts) p.max_steps = kPilotMaxAttempts;
   return p;
 }
 
@@ -184,6 +189,7 @@ int launch_cost_ordered(const LaunchArgs* a, size_t base_bytes, LaunchFn launch,
   p.ws_bytes = base_bytes;
   p.order = nullptr;
   p.pilot = 1;
+  p.carry = nullptr;    // the pilot restarts and leaves a carried state alone
   int rc = launch(&p, stream);
   if (rc) return rc;
   const unsigned chunks = (unsigned)((a->n + kOrderChunk - 1) / kOrderChunk);

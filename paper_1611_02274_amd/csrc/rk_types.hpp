@@ -40,6 +40,7 @@ struct LaunchArgs {
   const int32_t* order;  // [n] queue position -> system index, or null (position = index)
   int pilot;             // nonzero: a cost-order pilot (the same kernels under their own
                          // names, so a profile tells the two passes apart)
+  double* carry;         // [kCarryRows + N][n] controller state carried between calls, or null
 };
 
 // Enqueues the integration on the stream (a hipStream_t); 0 on success.
@@ -109,6 +110,7 @@ struct BatchNetArgs {
   const double* g;     // [2][n]
   int32_t* status;     // [n] or null
   int32_t* stats;      // [kNStats][n] or null
+  double* carry;       // [kCarryRows + N][n] carried controller state, or null (restart)
 };
 
 struct BatchArgs {

@@ -118,3 +118,37 @@ def test_batch_schedule_options(rk):
         got = _run(rk, batch, per_net, codes, dt, n_sub, "persistent", **kw)
         for part in range(3):
             assert _same_bits(got[part], base[part]), kw
+
+
+def test_batch_carried_state(rk, orc):
+    """Substeps with the controller state carried (per network [7 + N, n]
+    arrays): the persistent launch, both plain forms and a replayed graph agree
+    bit for bit, carried arrays included, and equal the oracle's carried
+    substeps."""
+    import torch
+    n_total, dt, n_sub = 2000, 2e-7, 4
+    say(f"case batch carry n={n_total} dt={dt} substeps={n_sub}")
+    nets, probs, batch, per_net, codes = _setup(rk, n_total, 23)
+    ref = []
+    for net, (y0, g) in zip(nets, per_net):
+        pb = orc.network(net)
+        c = orc.carry_init(pb, y0.shape[1])
+        y = y0.copy()
+        for k in range(n_sub):
+            y, s, st = orc.rkc_batch_carry(pb, y, g, c, k * dt, (k + 1) * dt, 1e-8, 1e-12)
+        ref.append((y, s, st, c))
+    outs = {}
+    for mode, graph in (("persistent", False), ("interleaved", False), ("per_network", False),
+                        ("persistent", True)):
+        carry = [torch.zeros((rk.carry_rows(p), y.shape[1]), dtype=torch.float64, device="cuda")
+                 for p, (y, _) in zip(probs, per_net)]
+        ys, st, stats = _run(rk, batch, per_net, codes, dt, n_sub, mode, use_graph=graph,
+                             carry=carry)
+        outs[(mode, graph)] = (ys, st, stats, [c.cpu().numpy() for c in carry])
+    base = outs[("persistent", False)]
+    for key, o in outs.items():
+        for a, b in zip(o, base):
+            assert _same_bits(a, b), key
+    for k, (yo, so, sto, co) in enumerate(ref):
+        compare(base[0][k], base[1][k], base[2][k], yo, so, sto, 1e-12, f"carry net{SIZES[k]}")
+        assert np.array_equal(base[3][k].view(np.int64), co.view(np.int64))

@@ -377,3 +377,51 @@ def test_pleiades_full_size_sampled(rk, orc):
         np.ascontiguousarray(y0[:, idx]), t0=w.t0, t1=w.t1)
     compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, 1e-10, "full pleiades sample")
     assert np.all(sg == 0)
+
+
+@pytest.mark.parametrize("problem,method,n,dt,k,schedules", [
+    ("net13", "rkc", 3000, 2e-7, 4, (1, 2)),
+    ("net13", "rkck", 1500, 1e-8, 4, (1, 2)),
+    ("net53", "rkc", 400, 2e-7, 3, (1, 3)),
+    ("net32", "rkck", 300, 5e-8, 3, (2, 3)),
+    ("vdp", "rkck", 2000, 0.5, 6, (1, 2)),
+])
+def test_carried_state_equals_oracle(rk, orc, problem, method, n, dt, k, schedules):
+    """Substeps with the controller state carried between calls and the state
+    perturbed between them: every schedule (one lane or a group per system,
+    with and without the cost order) gives the oracle's bits, carried arrays
+    included."""
+    import torch
+    say(f"case carry {problem} {method} n={n} substeps={k}")
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, 41)
+        prob, pb, atol = rk.Problem.vdp(), orc.vdp(), 1e-10
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, 41, (900.0, 2800.0))
+        prob, pb, atol = rk.Problem.network(net), orc.network(net), 1e-12
+    fo = orc.rkck_batch_carry if method == "rkck" else orc.rkc_batch_carry
+    fg = rk.integrate_rkck if method == "rkck" else rk.integrate_rkc
+
+    def bump(y, s):
+        return np.ascontiguousarray(y * (1.0 + 1e-3 * np.cos(np.arange(y.shape[1]) + s)))
+
+    co = orc.carry_init(pb, n)
+    yo = y0
+    for s in range(k):
+        yo1, so, sto = fo(pb, yo, g, co, s * dt, (s + 1) * dt, 1e-8, atol)
+        yo = bump(yo1, s)
+    gd = torch.from_numpy(g).cuda()
+    for sched in schedules:
+        for cost in (0, 1):
+            cg = torch.zeros((rk.carry_rows(prob), n), dtype=torch.float64, device="cuda")
+            yg = y0
+            for s in range(k):
+                y1, st, stats = fg(prob, torch.from_numpy(yg).cuda(), gd, s * dt, (s + 1) * dt,
+                                   1e-8, atol, schedule=sched, cost_order=cost, carry=cg)
+                torch.cuda.synchronize()
+                yg1 = y1.cpu().numpy()
+                yg = bump(yg1, s)
+            compare(yg1, st.cpu().numpy(), stats.cpu().numpy(), yo1, so, sto, atol,
+                    f"carry {problem} {method} schedule={sched} cost={cost}")
+            assert np.array_equal(cg.cpu().numpy().view(np.int64), co.view(np.int64))

@@ -80,3 +80,50 @@ def test_host_build_max_steps(orc):
     yo, so, sto = orc.rkc_batch(orc.network(net), y0, g, 0.0, 1e-6, 1e-8, 1e-12, max_steps=17)
     assert np.all(so == orc.MAXSTEPS)
     assert np.array_equal(sh, so) and np.array_equal(sth, sto) and np.array_equal(yh, yo)
+
+
+@pytest.mark.parametrize("method,problem,n,seed,dt,k,rtol,atol,T_range", [
+    ("rkc", "net13", 40, 2002, 1e-7, 6, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkck", "net13", 24, 12, 5e-9, 5, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkc", "vdp", 12, 3, 0.2, 8, 1e-8, 1e-10, None),
+    ("rkck", "vdp", 12, 4, 0.2, 8, 1e-8, 1e-10, None),
+    ("rkc", "net53", 6, 3003, 1e-7, 3, 1e-8, 1e-12, (900.0, 2800.0)),
+])
+def test_host_build_with_carried_state_equals_oracle(orc, method, problem, n, seed, dt, k, rtol,
+                                                     atol, T_range):
+    """Substeps with the controller state carried (the state modified between
+    calls, as an operator-split transport step would): the kernels' host
+    build reproduces the oracle's carried integration bit for bit, carried
+    arrays included."""
+    from paper_1611_02274_amd import _lib
+    import paper_1611_02274_amd as rk
+    if problem == "vdp":
+        y0, g = I.vdp_inputs(n, seed)
+        prob, pb = rk.Problem.vdp(), orc.vdp()
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, seed, T_range)
+        prob, pb = rk.Problem.network(net), orc.network(net)
+    f = _lib.lib().rkmi_test_host_integrate_carry
+    f.argtypes = [C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                  C.c_int64, C.c_void_p]
+    f.restype = C.c_int
+    ch = orc.carry_init(pb, n)
+    co = orc.carry_init(pb, n)
+    yh = yo = np.ascontiguousarray(y0)
+    g = np.ascontiguousarray(g)
+    fo = orc.rkck_batch_carry if method == "rkck" else orc.rkc_batch_carry
+    for s in range(k):
+        y1 = np.zeros_like(yh)
+        st = np.zeros(n, dtype=np.int32)
+        stats = np.zeros((6, n), dtype=np.int32)
+        assert f(0 if method == "rkck" else 1, prob.handle, n, yh.ctypes.data, y1.ctypes.data,
+                 g.ctypes.data, s * dt, (s + 1) * dt, rtol, atol, st.ctypes.data,
+                 stats.ctypes.data, 0, ch.ctypes.data) == 0
+        yo1, so, sto = fo(pb, yo, g, co, s * dt, (s + 1) * dt, rtol, atol)
+        assert np.array_equal(st, so) and np.array_equal(stats, sto)
+        assert np.array_equal(y1.view(np.int64), yo1.view(np.int64))
+        assert np.array_equal(ch.view(np.int64), co.view(np.int64))
+        # a transport-like change of the state between substeps
+        yh = yo = np.ascontiguousarray(yo1 * (1.0 + 1e-3 * np.cos(np.arange(n) + s)))
