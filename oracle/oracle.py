@@ -15,7 +15,7 @@ from . import build as _build
 
 _lib = None
 
-VDP, LINEAR, MASS_ACTION, PLEIADES = 1, 2, 3, 4
+VDP, LINEAR, MASS_ACTION, PLEIADES, MASS_ACTION_THERMAL = 1, 2, 3, 4, 5
 OK, NONFINITE, HMIN, MAXSTEPS = 0, 1, 2, 3
 NSTATS = 6
 ST_ACCEPT, ST_REJECT, ST_RHS, ST_SR_CALLS, ST_POW_ITERS, ST_MAX_STAGES = range(6)
@@ -28,7 +28,7 @@ _ip = C.POINTER(C.c_int32)
 class _Problem(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_eq", C.c_int), ("n_param", C.c_int), ("A", _dp),
                 ("n_rx", C.c_int), ("reac", _ip), ("prod", _ip), ("lnA", _dp), ("beta", _dp),
-                ("Ea", _dp), ("Keq", _dp), ("W", _dp)]
+                ("Ea", _dp), ("Keq", _dp), ("W", _dp), ("thermo", _dp)]
 
 
 def _d(a):
@@ -136,6 +136,10 @@ class Problem:
             s.lnA, s.beta, s.Ea = _d(arrs["lnA"]), _d(arrs["beta"]), _d(arrs["Ea"])
             s.Keq, s.W = _d(arrs["Keq"]), _d(arrs["W"])
             self.lnA = arrs["lnA"]
+            if kind == MASS_ACTION_THERMAL:
+                th = np.ascontiguousarray(np.stack([net.u0, net.cv0, net.cv1]), dtype=np.float64)
+                self._keep.append(th)
+                s.thermo = _d(th)
         self.s = s
         self.n_eq, self.n_param = n_eq, n_param
 
@@ -162,6 +166,11 @@ def linear(A):
 
 def network(net):
     return Problem(MASS_ACTION, net.n_sp, 2, net=net)
+
+
+def network_thermal(net):
+    """The network with the energy equation: state (T, Y_1..Y_N), g = (rho)."""
+    return Problem(MASS_ACTION_THERMAL, net.n_sp + 1, 1, net=net)
 
 
 def pleiades():

@@ -78,15 +78,21 @@ static int check_problem(const orc_problem *pb) {
        !pb->lnA || !pb->beta || !pb->Ea || !pb->Keq || !pb->W))
     return -1;
   if (pb->kind == ORC_PLEIADES && pb->n_eq != 28) return -1;
+  if (pb->kind == ORC_MASS_ACTION_THERMAL &&
+      (pb->n_eq < 2 || pb->n_rx <= 0 || pb->n_rx > ORC_MAXR || pb->n_param < 1 || !pb->reac ||
+       !pb->prod || !pb->lnA || !pb->beta || !pb->Ea || !pb->Keq || !pb->W || !pb->thermo))
+    return -1;
   if (pb->kind != ORC_VDP && pb->kind != ORC_LINEAR && pb->kind != ORC_MASS_ACTION &&
-      pb->kind != ORC_PLEIADES)
+      pb->kind != ORC_PLEIADES && pb->kind != ORC_MASS_ACTION_THERMAL)
     return -1;
   return 0;
 }
 
 /* Problems with vector-Jacobian products (every kind but Pleiades). */
 static int check_vjp_problem(const orc_problem *pb) {
-  return (check_problem(pb) || pb->kind == ORC_PLEIADES) ? -1 : 0;
+  return (check_problem(pb) || pb->kind == ORC_PLEIADES || pb->kind == ORC_MASS_ACTION_THERMAL)
+             ? -1
+             : 0;
 }
 
 /* Arrhenius rate coefficient k = A T^beta exp(-E/T) (Sec. 4.2), evaluated in
@@ -96,6 +102,11 @@ static int check_vjp_problem(const orc_problem *pb) {
 static void sys_init(orc_sys *S, const orc_problem *pb, const double *g) {
   S->pb = pb;
   for (int i = 0; i < pb->n_param; ++i) S->g[i] = g[i];
+  if (pb->kind == ORC_MASS_ACTION_THERMAL) {
+    S->rho = g[0];
+    S->irho = 1.0 / S->rho;
+    for (int k = 0; k < pb->n_eq - 1; ++k) S->invW[k] = 1.0 / pb->W[k];
+  }
   if (pb->kind == ORC_MASS_ACTION) {
     double T = g[0];
     double lnT = orc_cr_log(T);
@@ -124,6 +135,51 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
       for (int j = 0; j < N; ++j) s += pb->A[i * N + j] * y[j];
       f[i] = s;
     }
+  } else if (pb->kind == ORC_MASS_ACTION_THERMAL) {
+    /* Non-isothermal species equations at constant volume (Sec. 4.2): state
+     * (T, Y_1..Y_N);
+     *   dY_k/dt = W_k omega_k / rho,
+     *   dT/dt = -(1 / (rho c_v)) sum_k e_k omega_k W_k,  c_v = sum_k Y_k c_v,k(T),
+     * with the rate coefficients evaluated at the current T on every call,
+     * k_f,j = exp(ln A_j + beta_j ln T - Ea_j / T), k_r,j = k_f,j / K_j, and
+     * the synthetic per-mass internal energies e_k(T) = u0_k + (c_k + d_k T) T,
+     * c_v,k(T) = c_k + 2 d_k T.  Readings as the isothermal rate law (left to
+     * right, reciprocals of constants), plus: Ea_j / T as Ea_j times 1 / T
+     * formed once per call; the energy sum accumulated (e_k omega_k) W_k from
+     * zero in species order and scaled as -((sum / rho) / c_v) with 1 / rho. */
+    const int NS = N - 1;
+    const double T = y[0];
+    const double lnT = orc_cr_log(T);
+    const double invT = 1.0 / T;
+    const double *u0 = pb->thermo, *cc = pb->thermo + NS, *dd = pb->thermo + 2 * NS;
+    double kf[ORC_MAXR], kr[ORC_MAXR], C[ORC_MAXN], omega[ORC_MAXN];
+    for (int j = 0; j < pb->n_rx; ++j) {
+      kf[j] = orc_cr_exp(pb->lnA[j] + pb->beta[j] * lnT - pb->Ea[j] * invT);
+      kr[j] = kf[j] * (1.0 / pb->Keq[j]);
+    }
+    double M = 0.0;
+    for (int k = 0; k < NS; ++k) C[k] = (S->rho * y[1 + k]) * S->invW[k];
+    for (int k = 0; k < NS; ++k) M += C[k];
+    for (int k = 0; k < NS; ++k) omega[k] = 0.0;
+    for (int j = 0; j < pb->n_rx; ++j) {
+      int r0 = pb->reac[2 * j], r1 = pb->reac[2 * j + 1];
+      int p0 = pb->prod[2 * j], p1 = pb->prod[2 * j + 1];
+      double fwd = kf[j] * C[r0] * (r1 >= 0 ? C[r1] : M);
+      double rev = kr[j] * C[p0] * (p1 >= 0 ? C[p1] : M);
+      double q = fwd - rev;
+      omega[r0] -= q;
+      if (r1 >= 0) omega[r1] -= q;
+      omega[p0] += q;
+      if (p1 >= 0) omega[p1] += q;
+    }
+    for (int k = 0; k < NS; ++k) f[1 + k] = (pb->W[k] * omega[k]) * S->irho;
+    double sum = 0.0, cv = 0.0;
+    for (int k = 0; k < NS; ++k) {
+      const double e = u0[k] + (cc[k] + dd[k] * T) * T;
+      sum += (e * omega[k]) * pb->W[k];
+      cv += y[1 + k] * (cc[k] + 2.0 * dd[k] * T);
+    }
+    f[0] = -((sum * S->irho) / cv);
   } else if (pb->kind == ORC_PLEIADES) {
     /* Pleiades problem (Sec. 4.1): seven bodies of mass m_i = i (1-based) in the
      * plane, state (x_1..x_7, y_1..y_7, x_1'..x_7', y_1'..y_7'); z'' = f(z) as

@@ -29,7 +29,8 @@
 #define ORC_MAXR 2048     /* max reactions */
 #define ORC_MAXP 8        /* max per-system parameters */
 
-enum { ORC_VDP = 1, ORC_LINEAR = 2, ORC_MASS_ACTION = 3, ORC_PLEIADES = 4 };
+enum { ORC_VDP = 1, ORC_LINEAR = 2, ORC_MASS_ACTION = 3, ORC_PLEIADES = 4,
+       ORC_MASS_ACTION_THERMAL = 5 };
 
 /* per-system status */
 enum { ORC_OK = 0, ORC_NONFINITE = 1, ORC_HMIN = 2, ORC_MAXSTEPS = 3 };
@@ -58,7 +59,8 @@ typedef struct {
   int kind;            /* ORC_VDP | ORC_LINEAR | ORC_MASS_ACTION | ORC_PLEIADES */
   int n_eq;            /* N (Pleiades: 28) */
   int n_param;         /* entries of g per system: vdp 1 (mu), linear 0, mass action 2 (T, rho),
-                          Pleiades 0 */
+                          Pleiades 0, thermal mass action 1 (rho); n_eq = n_sp + 1 for the
+                          thermal kind (row 0 is T) */
   const double *A;     /* ORC_LINEAR: f = A y, A row-major [N][N] */
   int n_rx;            /* ORC_MASS_ACTION: reactions */
   const int32_t *reac; /* [n_rx][2] species index per reactant slot, -1 = empty */
@@ -68,6 +70,8 @@ typedef struct {
   const double *Ea;    /* [n_rx] activation temperature E/R, K */
   const double *Keq;   /* [n_rx] equilibrium constant k_f / k_r */
   const double *W;     /* [n_sp] molar masses */
+  const double *thermo;/* ORC_MASS_ACTION_THERMAL: [3][n_sp] (u0, c, d): e_k(T) = u0 + (c + d T) T,
+                          c_v,k(T) = c + 2 d T, per unit mass */
 } orc_problem;
 
 #ifdef __cplusplus

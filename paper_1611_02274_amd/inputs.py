@@ -63,6 +63,11 @@ class Network:
     Ea: np.ndarray
     Keq: np.ndarray
     seed: int = -1
+    # synthetic thermodynamics (networks with the energy equation only): per
+    # unit mass, e_k(T) = u0_k + (cv0_k + cv1_k T) T, c_v,k(T) = cv0_k + 2 cv1_k T
+    u0: np.ndarray | None = None
+    cv0: np.ndarray | None = None
+    cv1: np.ndarray | None = None
 
     def stoich(self) -> np.ndarray:
         """nu[k, j] = (count of k among products) - (count among reactants)."""
@@ -161,6 +166,30 @@ def make_network(n_sp: int, n_rx: int, seed: int) -> Network:
 def standard_network(n_sp: int) -> Network:
     """The four fixed networks (9/19, 13/27, 32/133, 53/325)."""
     return make_network(n_sp, NETWORK_SIZES[n_sp], NETWORK_SEEDS[n_sp])
+
+
+THERMO_SEED_OFFSET = 7000
+
+
+def thermal_network(n_sp: int) -> Network:
+    """A standard network with seeded synthetic thermodynamics for the energy
+    equation (per unit mass, erg/g): cv0 = (R_u / W) U[1.5, 3.5], cv1 = cv0
+    U[0, 1e-4] / K, u0 = (R_u / W) U[-2000, 2000] K."""
+    net = standard_network(n_sp)
+    rng = np.random.default_rng(THERMO_SEED_OFFSET + n_sp)
+    rw = R_UNIVERSAL / net.W
+    cv0 = rw * rng.uniform(1.5, 3.5, n_sp)
+    cv1 = cv0 * rng.uniform(0.0, 1e-4, n_sp)
+    u0 = rw * rng.uniform(-2000.0, 2000.0, n_sp)
+    return dataclasses.replace(net, u0=u0, cv0=cv0, cv1=cv1)
+
+
+def thermal_inputs(net: Network, n: int, seed: int, T_range=(1000.0, 2500.0)):
+    """(y0 [N + 1, n] = (T0, Y0), g [1, n] = (rho)) with T0 ~ U[T_range],
+    Y0 ~ Dirichlet(1), rho from (T0, Y0) at 1 atm (held constant: constant volume)."""
+    Y, g2 = kinetics_inputs(net, n, seed, T_range)
+    y0 = np.ascontiguousarray(np.concatenate([g2[:1], Y]))
+    return y0, np.ascontiguousarray(g2[1:2])
 
 
 def density(net: Network, T: np.ndarray, Y: np.ndarray) -> np.ndarray:
