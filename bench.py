@@ -51,10 +51,12 @@ def cpu_baseline(w, net, y0, g, target_s: float):
 
     from oracle import oracle as orc
     pleiades = isinstance(net, str)
-    pb = orc.vdp() if net is None else orc.pleiades() if pleiades else orc.network(net)
+    thermal = w.problem.endswith("_thermal")
+    pb = (orc.vdp() if net is None else orc.pleiades() if pleiades
+          else orc.network_thermal(net) if thermal else orc.network(net))
     fn = orc.rkck_batch if w.method == "rkck" else orc.rkc_batch
     cores = orc.max_threads()
-    n_global = 10 if pleiades else 1
+    n_global = w.global_steps
 
     def run(m):
         idx = np.unique(np.linspace(0, w.n - 1, m).astype(np.int64))
@@ -356,8 +358,9 @@ def main():
     if args.n > 0:
         import dataclasses
         w = dataclasses.replace(w, n=args.n)
+    thermal = w.problem.endswith("_thermal")
     net = (None if w.problem == "vdp" else FL.PLEIADES if w.problem == "pleiades"
-           else I.network_of(w.problem))
+           else I.thermal_network(int(w.problem[3:-8])) if thermal else I.network_of(w.problem))
     if "_adjoint" in w.name:
         adjoint_bench(args, w, net)
         return
@@ -366,13 +369,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prob = (rk.Problem.vdp() if net is None else rk.Problem.pleiades() if net == FL.PLEIADES
-            else rk.Problem.network(net))
+            else rk.Problem.network_thermal(net) if thermal else rk.Problem.network(net))
     yd = torch.from_numpy(y0).to(dev)
     gd = torch.from_numpy(g).to(dev) if g is not None else None
     out = torch.empty_like(yd)
-    # the Pleiades workload integrates [t0, t1] in ten global steps, each a
-    # restart (Sec. 4.1); every other workload in one call
-    n_global = 10 if w.problem == "pleiades" else 1
+    # [t0, t1] in w.global_steps global steps, each a restart (Sec. 3)
+    n_global = w.global_steps
     status = torch.empty(w.n, dtype=torch.int32, device=dev)
     stats = [torch.empty((rk.RK_NSTATS, w.n), dtype=torch.int32, device=dev)
              for _ in range(n_global)]
@@ -426,7 +428,8 @@ def main():
     st_all = [x.cpu().numpy() for x in stats]
     st_h = sum(x.astype(np.int64) for x in st_all)
     status_h = status.cpu().numpy()
-    flops = sum(FL.total(w.method, x, prob.n_eq, net) for x in st_all)
+    flops = sum(FL.total(w.method, x, prob.n_eq, FL.Thermal(net) if thermal else net)
+                for x in st_all)
     achieved = flops / (kern_ms * 1e-3) / 1e12
     traffic, traffic_src = measured_traffic(w.name)
     value = w.n * args.steps / elapsed

@@ -132,6 +132,20 @@ int rk_problem_create_pleiades(rk_problem *out);
  * generator); RK_EUNSUPPORTED otherwise. */
 int rk_problem_create_mass_action(const rk_mech_desc *desc, rk_problem *out);
 
+/* The network of *desc with the energy equation of Sec. 4.2 at constant
+ * volume (adiabatic): state (T, Y_1..Y_N), N + 1 unknowns, row 0 = T in
+ * kelvin; one parameter per system, g row 0 = rho (constant);
+ *   dY_k/dt = W_k omega_k / rho  (omega_k as rk_problem_create_mass_action,
+ *             with k_f,j = exp(lnA_j + beta_j ln T - Ea_j / T) at the current T),
+ *   dT/dt   = -(sum_k e_k omega_k W_k) / (rho c_v),  c_v = sum_k Y_k c_v,k(T),
+ *   e_k(T)  = u0_k + (cv0_k + cv1_k T) T,  c_v,k(T) = cv0_k + 2 cv1_k T
+ * (per unit mass; u0, cv0, cv1: host arrays of n_sp, copied).  Compiled for
+ * networks of up to 15 species whose topology the code generator was given
+ * with the energy equation; RK_EUNSUPPORTED otherwise.  No adjoint. */
+int rk_problem_create_mass_action_thermal(const rk_mech_desc *desc, const double *u0,
+                                          const double *cv0, const double *cv1,
+                                          rk_problem *out);
+
 /* Releases a problem handle and its device copies (NULL is ignored).  No
  * integration using it may still be pending on any stream. */
 void rk_problem_destroy(rk_problem p);

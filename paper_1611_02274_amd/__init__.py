@@ -46,6 +46,36 @@ class Problem:
         return cls(h, "pleiades")
 
     @classmethod
+    def network_thermal(cls, net) -> "Problem":
+        """The network with the energy equation (state (T, Y), g = (rho)); net
+        must carry its thermodynamics (inputs.thermal_network)."""
+        import numpy as np
+        keep, d = cls._desc(net)
+        th = [np.ascontiguousarray(a, dtype=np.float64) for a in (net.u0, net.cv0, net.cv1)]
+        h = C.c_void_p()
+        _lib.check(_lib.lib().rk_problem_create_mass_action_thermal(
+            C.byref(d), th[0].ctypes.data, th[1].ctypes.data, th[2].ctypes.data, C.byref(h)))
+        return cls(h, "mass_action_thermal", net)
+
+    @staticmethod
+    def _desc(net):
+        import numpy as np
+        keep = dict(
+            reac=np.ascontiguousarray(net.reac, dtype=np.int32),
+            prod=np.ascontiguousarray(net.prod, dtype=np.int32),
+            lnA=np.ascontiguousarray(net.lnA, dtype=np.float64),
+            beta=np.ascontiguousarray(net.beta, dtype=np.float64),
+            Ea=np.ascontiguousarray(net.Ea, dtype=np.float64),
+            Keq=np.ascontiguousarray(net.Keq, dtype=np.float64),
+            W=np.ascontiguousarray(net.W, dtype=np.float64))
+        ip, dp = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        d = _lib.MechDesc(net.n_sp, net.n_rx, keep["reac"].ctypes.data_as(ip),
+                          keep["prod"].ctypes.data_as(ip), keep["lnA"].ctypes.data_as(dp),
+                          keep["beta"].ctypes.data_as(dp), keep["Ea"].ctypes.data_as(dp),
+                          keep["Keq"].ctypes.data_as(dp), keep["W"].ctypes.data_as(dp))
+        return keep, d
+
+    @classmethod
     def network(cls, net) -> "Problem":
         import numpy as np
         keep = dict(

@@ -67,6 +67,8 @@ def lib():
         L.rk_problem_create_vdp.argtypes = [C.POINTER(vp)]
         L.rk_problem_create_pleiades.argtypes = [C.POINTER(vp)]
         L.rk_problem_create_mass_action.argtypes = [C.POINTER(MechDesc), C.POINTER(vp)]
+        L.rk_problem_create_mass_action_thermal.argtypes = [C.POINTER(MechDesc), dp, dp, dp,
+                                                            C.POINTER(vp)]
         L.rk_problem_destroy.argtypes = [vp]
         L.rk_problem_destroy.restype = None
         L.rk_problem_dims.argtypes = [vp, i32p, i32p, i32p]

@@ -24,6 +24,8 @@ ARCH = "gfx950"
 COMPILED_NETWORKS = (9, 13, 32, 53)
 # Ragged batches compiled as one kernel (species counts, in order).
 COMPILED_BATCHES = ((9, 13, 32, 53),)
+# Networks also compiled with the energy equation (state T, Y; up to 15 species).
+COMPILED_THERMAL = (9, 13)
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -42,7 +44,8 @@ def sources():
     gen_crmath.generate()
     nets = [standard_network(k) for k in COMPILED_NETWORKS]
     batches = [[standard_network(k) for k in b] for b in COMPILED_BATCHES]
-    gen = codegen.generate(nets, batches=batches)
+    thermal = [standard_network(k) for k in COMPILED_THERMAL]
+    gen = codegen.generate(nets, batches=batches, thermal=thermal)
     hand = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")]
     return hand + gen
 

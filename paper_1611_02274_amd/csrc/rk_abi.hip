@@ -52,7 +52,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-enum Kind { kVdp = 1, kMassAction = 3, kPleiades = 4 };
+enum Kind { kVdp = 1, kMassAction = 3, kPleiades = 4, kMassActionThermal = 5 };
 
 }  // namespace
 
@@ -284,8 +284,13 @@ int rk_problem_create_pleiades(rk_problem* out) {
   return RK_OK;
 }
 
-int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// A compiled mass-action network, isothermal (thermo = NULL) or with the
+// energy equation (thermo = [u0 | cv0 | cv1], n_sp each).
+int create_mass_action(const rk_mech_desc* d, const double* thermo, rk_problem* out) {
   if (!out) return fail(RK_EINVAL, "out is NULL");
   *out = nullptr;
   if (!d) return fail(RK_EINVAL, "desc is NULL");
@@ -311,6 +316,7 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
   int hit_index = -1;
   for (int e = 0; e < rkmi::kGenRegistrySize; ++e) {
     const rkmi::GenEntry& E = rkmi::kGenRegistry[e];
+    if (E.thermal != (thermo ? 1 : 0)) continue;
     if (E.n_sp == d->n_sp && E.n_rx == d->n_rx &&
         !std::memcmp(E.reac, d->reac, sizeof(int32_t) * 2 * d->n_rx) &&
         !std::memcmp(E.prod, d->prod, sizeof(int32_t) * 2 * d->n_rx)) {
@@ -321,15 +327,15 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
   }
   if (!hit)
     return fail(RK_EUNSUPPORTED,
-                "no compiled right-hand side for this %d-species / %d-reaction topology; "
+                "no compiled right-hand side for this %d-species / %d-reaction topology%s; "
                 "generate it with the package code generator and rebuild",
-                d->n_sp, d->n_rx);
+                d->n_sp, d->n_rx, thermo ? " with the energy equation" : "");
   rk_problem p = new (std::nothrow) rk_problem_s();
   if (!p) return fail(RK_ENOMEM, "out of host memory");
-  p->kind = kMassAction;
-  p->n_eq = d->n_sp;
-  p->n_param = 2;
-  p->n_theta = d->n_rx;
+  p->kind = thermo ? kMassActionThermal : kMassAction;
+  p->n_eq = d->n_sp + (thermo ? 1 : 0);
+  p->n_param = thermo ? 1 : 2;
+  p->n_theta = thermo ? 0 : d->n_rx;
   p->n_rx = d->n_rx;
   p->launch = hit->launch;
   p->host = hit->host;
@@ -340,7 +346,7 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
   p->adjoint_host = hit->adjoint_host;
   p->gen_index = hit_index;
   const int nr = d->n_rx, ns = d->n_sp;
-  p->host_prm.resize(4 * nr + 2 * ns);
+  p->host_prm.resize(4 * nr + (thermo ? 5 : 2) * ns);
   for (int j = 0; j < nr; ++j) {
     p->host_prm[j] = d->lnA[j];
     p->host_prm[nr + j] = d->beta[j];
@@ -351,8 +357,39 @@ int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
     p->host_prm[4 * nr + k] = d->W[k];
     p->host_prm[4 * nr + ns + k] = 1.0 / d->W[k];
   }
+  if (thermo)
+    for (int k = 0; k < 3 * ns; ++k) p->host_prm[4 * nr + 2 * ns + k] = thermo[k];
   *out = p;
   return RK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rk_problem_create_mass_action(const rk_mech_desc* d, rk_problem* out) {
+  g_err.clear();
+  return create_mass_action(d, nullptr, out);
+}
+
+int rk_problem_create_mass_action_thermal(const rk_mech_desc* d, const double* u0,
+                                          const double* cv0, const double* cv1,
+                                          rk_problem* out) {
+  g_err.clear();
+  if (!d || !u0 || !cv0 || !cv1 || !out) {
+    if (out) *out = nullptr;
+    return fail(RK_EINVAL, "desc, u0, cv0, cv1 and out are required");
+  }
+  if (d->n_sp <= 0 || d->n_sp > 4096) return fail(RK_EINVAL, "bad n_sp");
+  std::vector<double> th(3 * (size_t)d->n_sp);
+  for (int k = 0; k < d->n_sp; ++k) {
+    th[k] = u0[k];
+    th[d->n_sp + k] = cv0[k];
+    th[2 * d->n_sp + k] = cv1[k];
+    if (!std::isfinite(u0[k]) || !(cv0[k] > 0.0) || !std::isfinite(cv1[k]))
+      return fail(RK_EINVAL, "species %d has invalid thermodynamic data", k);
+  }
+  return create_mass_action(d, th.data(), out);
 }
 
 void rk_problem_destroy(rk_problem p) {

@@ -97,6 +97,7 @@ struct GenEntry {
   taped_host_fn taped_host;
   adjoint_fn adjoint;
   adjoint_host_fn adjoint_host;
+  int thermal;                    // 1: compiled with the energy equation (state T, Y)
 };
 
 // Ragged batch of several compiled networks (rk_batch.hpp).

@@ -37,9 +37,21 @@ ST_ACCEPT, ST_REJECT, ST_RHS, ST_SR_CALLS, ST_POW_ITERS, ST_MAX_STAGES = range(6
 PLEIADES = "pleiades"      # stands for the Pleiades problem where a network is expected
 
 
+class Thermal:
+    """A network with the energy equation: the isothermal right-hand side plus,
+    per evaluation, the rate coefficients' arguments lnA + b lnT - E (1/T)
+    (3 NR flops; NR exp and one log are special) and the energy sum
+    (e_k: 4, sum: 2, c_v,k and its sum: 4 per species; 1 more for the scale)."""
+
+    def __init__(self, net):
+        self.net = net
+
+
 def rhs_flops(net=None) -> int:
     if net is None:
         return 5
+    if isinstance(net, Thermal):
+        return rhs_flops(net.net) + 3 * net.net.n_rx + 10 * net.net.n_sp + 1
     if isinstance(net, str) and net == PLEIADES:
         return 21 * 6 + 42 * 2 * 3
 
@@ -48,7 +60,7 @@ def rhs_flops(net=None) -> int:
 
 
 def setup_flops(net=None) -> int:
-    return 0 if net is None or isinstance(net, str) else 5 * net.n_rx
+    return 0 if net is None or isinstance(net, (str, Thermal)) else 5 * net.n_rx
 
 
 def per_system(method: str, stats: np.ndarray, n_eq: int, net=None) -> np.ndarray:

@@ -258,6 +258,8 @@ class Workload:
     # keyword arguments of the integration call the benchmark times (schedule,
     # cost order); tests that check the benchmark's launch use the same
     launch: dict = dataclasses.field(default_factory=dict)
+    # [t0, t1] integrated in this many equal global steps, each a restart
+    global_steps: int = 1
 
 
 WORKLOADS = {
@@ -271,7 +273,11 @@ WORKLOADS = {
                            (900.0, 2800.0)),
     # ten global steps of 0.1 over [0, 1], each a restart (Sec. 4.1); eps = 1e-10
     "pleiades_rkck": Workload("pleiades_rkck", "rkck", "pleiades", 1 << 18, 0.0, 1.0, 1e-10, 0.0,
-                              6006, launch=dict(schedule=1)),
+                              6006, launch=dict(schedule=1), global_steps=10),
+    # the energy equation: ten global steps of 1e-6 s, each a restart (Sec. 4.2)
+    "net13_thermal_rkc": Workload("net13_thermal_rkc", "rkc", "net13_thermal", 1 << 18, 0.0,
+                                  1e-5, 1e-8, 1e-12, 8008, (1000.0, 2500.0),
+                                  launch=dict(schedule=1, cost_order=1), global_steps=10),
     "net13_adjoint": Workload("net13_adjoint", "rkc", "net13", 1 << 16, 0.0, 1e-6, 1e-8, 1e-12,
                               5005, (1000.0, 2500.0)),
     "net13_adjoint_rkck": Workload("net13_adjoint_rkck", "rkck", "net13", 1 << 16, 0.0, 1e-6,
@@ -292,6 +298,8 @@ def workload_inputs(w: Workload, n: int | None = None):
         return vdp_inputs(n, w.seed)
     if w.problem == "pleiades":
         return pleiades_inputs(n, w.seed)
+    if w.problem.endswith("_thermal"):
+        return thermal_inputs(thermal_network(int(w.problem[3:-8])), n, w.seed, w.T_range)
     return kinetics_inputs(network_of(w.problem), n, w.seed, w.T_range)
 
 

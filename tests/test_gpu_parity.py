@@ -425,3 +425,45 @@ def test_carried_state_equals_oracle(rk, orc, problem, method, n, dt, k, schedul
             compare(yg1, st.cpu().numpy(), stats.cpu().numpy(), yo1, so, sto, atol,
                     f"carry {problem} {method} schedule={sched} cost={cost}")
             assert np.array_equal(cg.cpu().numpy().view(np.int64), co.view(np.int64))
+
+
+@pytest.mark.parametrize("n_sp,method,n,t1,schedule,cost_order", [
+    (13, "rkc", 4133, 1e-6, 1, 0), (13, "rkc", 4133, 1e-6, 2, 1), (9, "rkc", 2000, 1e-6, 2, 0),
+    (13, "rkck", 700, 5e-8, 1, 1)])
+def test_thermal_networks(rk, orc, n_sp, method, n, t1, schedule, cost_order):
+    """Networks with the energy equation (state T, Y; rate coefficients at the
+    current T): every schedule equals the oracle."""
+    say(f"case thermal net{n_sp} {method} n={n} schedule={schedule} cost={cost_order}")
+    net = I.thermal_network(n_sp)
+    y0, g = I.thermal_inputs(net, n, 8100 + n_sp, (1000.0, 2500.0))
+    prob, pb = rk.Problem.network_thermal(net), orc.network_thermal(net)
+    yg, sg, stg = _gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, 1e-12, schedule=schedule,
+                       cost_order=cost_order)
+    yo, so, sto = _orc(orc, method, pb, y0, g, 0.0, t1, 1e-8, 1e-12)
+    compare(yg, sg, stg, yo, so, sto, 1e-12, f"thermal net{n_sp} {method}")
+
+
+def test_thermal_full_size_sampled(rk, orc):
+    """The 2^18-system 13-species workload with the energy equation in the
+    benchmark's launch, ten global steps of 1e-6 s; the oracle recomputes a
+    spread sample of 128 systems."""
+    import torch
+    w = I.WORKLOADS["net13_thermal_rkc"]
+    say(f"case full-size {w.name} n={w.n}")
+    net = I.thermal_network(13)
+    y0, g = I.workload_inputs(w)
+    prob, pb = rk.Problem.network_thermal(net), orc.network_thermal(net)
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    dt = (w.t1 - w.t0) / w.global_steps
+    for k in range(w.global_steps):
+        y1, st, stats = rk.integrate_rkc(prob, yd, gd, w.t0 + k * dt, w.t0 + (k + 1) * dt, w.rtol,
+                                         w.atol, out=yd, **w.launch)
+    torch.cuda.synchronize()
+    yg, sg, stg = yd.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy()
+    idx = np.unique(np.linspace(0, w.n - 1, 128).astype(np.int64))
+    yo = np.ascontiguousarray(y0[:, idx])
+    gs = np.ascontiguousarray(g[:, idx])
+    for k in range(w.global_steps):
+        yo, so, sto = orc.rkc_batch(pb, yo, gs, w.t0 + k * dt, w.t0 + (k + 1) * dt, w.rtol, w.atol)
+    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, "full thermal sample")
+    assert np.all(sg == 0)

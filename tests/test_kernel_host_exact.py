@@ -43,6 +43,10 @@ CASES = [
     ("rkc", "net53", 12, 3003, 0.0, 1e-6, 1e-8, 1e-12, (900.0, 2800.0)),
     ("rkck", "net32", 8, 31, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
     ("rkck", "net53", 8, 3003, 0.0, 2e-7, 1e-8, 1e-12, (900.0, 2800.0)),
+    # networks with the energy equation (state T, Y)
+    ("rkc", "net13_thermal", 48, 8008, 0.0, 1e-6, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkc", "net9_thermal", 48, 8009, 0.0, 1e-6, 1e-8, 1e-12, (1000.0, 2500.0)),
+    ("rkck", "net13_thermal", 16, 8010, 0.0, 5e-8, 1e-8, 1e-12, (1000.0, 2500.0)),
     # the Pleiades problem (28 unknowns in slot columns), one global step
     ("rkck", "pleiades", 24, 6006, 0.0, 0.1, 1e-10, 0.0, None),
     ("rkck", "pleiades", 8, 6007, 0.5, 0.6, 1e-12, 1e-14, None),
@@ -60,6 +64,10 @@ def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, 
     elif problem == "pleiades":
         y0, g = I.pleiades_inputs(n, seed)
         prob, pb = rk.Problem.pleiades(), orc.pleiades()
+    elif problem.endswith("_thermal"):
+        net = I.thermal_network(int(problem[3:-8]))
+        y0, g = I.thermal_inputs(net, n, seed, T_range)
+        prob, pb = rk.Problem.network_thermal(net), orc.network_thermal(net)
     else:
         net = I.network_of(problem)
         y0, g = I.kinetics_inputs(net, n, seed, T_range)
