@@ -110,8 +110,15 @@ __device__ void batch_run_net(const BatchNet& d, Ctl c, int refill, unsigned lon
   }
 }
 
+// The ragged kernel holds every network's code, so the register allocator
+// sizes it for the largest (the 53-species group RKC) and would run one wave
+// per SIMD; two waves, with a few hundred bytes of spills outside the stage
+// loops, hide the group exchanges' LDS latency (1.8x on the four-network batch).
+constexpr int kRaggedWavesPerEu = 2;
+
 template <class... P>
-__global__ __launch_bounds__(kLdsStride) void ragged_kernel(BatchParams bp, Ctl c) {
+__global__ __launch_bounds__(kLdsStride)
+__attribute__((amdgpu_waves_per_eu(kRaggedWavesPerEu))) void ragged_kernel(BatchParams bp, Ctl c) {
   __shared__ double lds[batch_lds_doubles<P...>()];
   double* const colbase = bp.cols ? bp.cols + (int64_t)blockIdx.x * bp.col_block : nullptr;
   for (int r = 0; r < bp.n_net; ++r) {

@@ -691,8 +691,26 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
   }
 }
 
+// Waves per SIMD the group kernel of a method is compiled for: a group problem
+// may ask for more than the register allocator would choose by itself
+// (GP::kWavesPerEuRkc, GP::kWavesPerEuRkck), spilling a few values that live
+// across attempts in exchange for a second wave to hide LDS latency.
+template <class GP, int Method, class = void>
+struct GroupWavesPerEu {
+  static constexpr int value = 1;
+};
+template <class GP>
+struct GroupWavesPerEu<GP, kMethodRkc, std::void_t<decltype(GP::kWavesPerEuRkc)>> {
+  static constexpr int value = GP::kWavesPerEuRkc;
+};
+template <class GP>
+struct GroupWavesPerEu<GP, kMethodRkck, std::void_t<decltype(GP::kWavesPerEuRkck)>> {
+  static constexpr int value = GP::kWavesPerEuRkck;
+};
+
 template <class GP, int Method, bool kPilot = false>
-__global__ __launch_bounds__(kLdsStride) void group_persistent_kernel(
+__global__ __launch_bounds__(kLdsStride)
+__attribute__((amdgpu_waves_per_eu(GroupWavesPerEu<GP, Method>::value))) void group_persistent_kernel(
     typename GP::Params prm, int64_t n, const double* y0, double* y1,
     const double* __restrict__ g, Ctl c, int32_t* __restrict__ status,
     int32_t* __restrict__ stats, unsigned long long* queue, const int32_t* __restrict__ order,
