@@ -88,11 +88,9 @@ RKMI_HD double scale2(double x, int m) {
   return x * pow2i(m);
 }
 
-// exp(zh + zl) rounded to nearest, |zl| <= ulp(zh).
-RKMI_HD double exp_dd(double zh, double zl) {
-  if (zh != zh) return zh;
-  if (zh > 709.782712893384) return __builtin_huge_val();
-  if (zh < -745.1332191019412) return 0.0;
+// exp(zh + zl) = 2^m (R.hi + R.lo) as a double-double R in [1 - 2^-11, 2 + 2^-10]
+// and an exponent m, for zh within exp_dd's finite range and |zl| <= ulp(zh).
+RKMI_HD dd exp_core(double zh, double zl, int& m_out) {
   // z = k ln2/1024 + r, |r| <= ln2/2048
   const double kd = rint(zh * kInvL);
   const double rh = zh - kd * kL1;                 // exact
@@ -119,8 +117,21 @@ RKMI_HD double exp_dd(double zh, double zl) {
   const int jj = (int)(k - (m << 10));
   const int j1 = jj >> 5, j2 = jj & 31;
   const dd T = dd_mul(dd{kExpT1[2 * j1], kExpT1[2 * j1 + 1]}, dd{kExpT2[2 * j2], kExpT2[2 * j2 + 1]});
-  const dd R = dd_mul(T, E);
-  return scale2(R.hi + R.lo, (int)m);
+  m_out = (int)m;
+  return dd_mul(T, E);
+}
+
+constexpr double kExpMaxArg = 709.782712893384;
+constexpr double kExpMinArg = -745.1332191019412;
+
+// exp(zh + zl) rounded to nearest, |zl| <= ulp(zh).
+RKMI_HD double exp_dd(double zh, double zl) {
+  if (zh != zh) return zh;
+  if (zh > kExpMaxArg) return __builtin_huge_val();
+  if (zh < kExpMinArg) return 0.0;
+  int m = 0;
+  const dd R = exp_core(zh, zl, m);
+  return scale2(R.hi + R.lo, m);
 }
 
 // log1p(u) for a double-double u with |u| <= 2^-9:
@@ -205,6 +216,34 @@ RKMI_HD double pow_from_log_nonneg(double x, dd L, double y) {
   if (y == 0.0 || x == 1.0) return 1.0;
   if (x == 0.0) return y < 0.0 ? __builtin_huge_val() : 0.0;
   return pow_from_log(L, y);
+}
+
+// x^y and x^(2y) for x in [0, 1] and 0 < y <= 1/3, given L = log_of_nonneg(x):
+// x^(2y) is the double-double square of x^y before its rounding (relative
+// error below about 2^-86), so both are the correctly rounded values that
+// pow_from_log_nonneg gives for y and 2y, for one exp instead of two.  In this
+// range both results are normal numbers (x^(2y) >= 2^-716).
+RKMI_HD void pow_pair_from_log_unit(double x, dd L, double y, double& p1, double& p2) {
+  if (x == 1.0) {
+    p1 = p2 = 1.0;
+    return;
+  }
+  if (x == 0.0) {
+    p1 = p2 = 0.0;
+    return;
+  }
+  dd z = two_prod(y, L.hi);
+  z.lo += y * L.lo;
+  if (z.hi < kExpMinArg) {        // outside the stated range: the general path
+    p1 = exp_dd(z.hi, z.lo);
+    p2 = pow_from_log(L, 2.0 * y);
+    return;
+  }
+  int m = 0;
+  const dd R = exp_core(z.hi, z.lo, m);
+  p1 = scale2(R.hi + R.lo, m);
+  const dd R2 = dd_mul(R, R);
+  p2 = scale2(R2.hi + R2.lo, 2 * m);
 }
 
 // x^y with the special values of C99 Annex F (y finite and not an integer

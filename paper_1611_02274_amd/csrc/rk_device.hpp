@@ -412,42 +412,96 @@ RKMI_HD void rkck_stats(const RkckState<Prob>& S, int32_t (&st)[kNStats]) {
 // =========================================================================
 constexpr double kKappa = 2.0 / 13.0;
 
-// omega_0 = 1 + kappa / s^2 and omega_1 = T_s'(omega_0) / T_s''(omega_0) from
-// the Chebyshev recurrence and its first two derivatives.
-RKMI_HD void rkc_omegas(int s, double& w0, double& w1) {
-  w0 = 1.0 + kKappa / ((double)s * (double)s);
-  double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
-  for (int j = 2; j <= s; ++j) {
+// The coefficients of an s-stage step depend on s alone: omega_0 = 1 + kappa /
+// s^2, omega_1 = T_s'(omega_0) / T_s''(omega_0) from the Chebyshev recurrence
+// and its first two derivatives, b_j = T_j'' / T_j'^2 (b_0 = b_1 = b_2),
+// a_j = 1 - b_j T_j, and per stage j >= 2 mu_j = 2 b_j omega_0 / b_{j-1},
+// nu_j = -b_j / b_{j-2}, mut_j = 2 b_j omega_1 / b_{j-1}, gt_j = -a_{j-1} mut_j
+// (the first stage uses mut_1 = b_1 omega_1).  RkcCoef runs the recurrences
+// one stage at a time.
+struct RkcStageCoef {
+  double mu, nu, mut, gt, c0;   // c0 = 1 - mu - nu
+};
+
+struct RkcCoef {
+  double w0 = 0.0, w1 = 0.0;
+  double Tm2 = 1.0, Tm1 = 0.0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
+  double bjm1 = 0.0, bjm2 = 0.0, ajm1 = 0.0;
+
+  constexpr __host__ __device__ explicit RkcCoef(int s) {
+    w0 = 1.0 + kKappa / ((double)s * (double)s);
+    double tm2 = 1.0, tm1 = w0, dm2 = 0.0, dm1 = 1.0, em2 = 0.0, em1 = 0.0;
+    for (int j = 2; j <= s; ++j) {
+      const double tj = 2.0 * w0 * tm1 - tm2;
+      const double dj = 2.0 * tm1 + 2.0 * w0 * dm1 - dm2;
+      const double ej = 4.0 * dm1 + 2.0 * w0 * em1 - em2;
+      tm2 = tm1; tm1 = tj;
+      dm2 = dm1; dm1 = dj;
+      em2 = em1; em1 = ej;
+    }
+    w1 = dm1 / em1;
+    Tm1 = w0;
+    const double D2 = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
+    const double E2 = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
+    bjm1 = E2 / (D2 * D2);
+    bjm2 = bjm1;
+    ajm1 = 1.0 - bjm1 * w0;
+  }
+  constexpr __host__ __device__ double mut1() const { return bjm1 * w1; }
+  // Coefficients of the next stage (j = 2, 3, ... in turn).
+  constexpr __host__ __device__ RkcStageCoef next() {
     const double Tj = 2.0 * w0 * Tm1 - Tm2;
     const double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
     const double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
+    const double bj = Ej / (Dj * Dj);
+    RkcStageCoef c{};
+    c.mu = 2.0 * bj * w0 / bjm1;
+    c.nu = -bj / bjm2;
+    c.mut = 2.0 * bj * w1 / bjm1;
+    c.gt = -ajm1 * c.mut;
+    c.c0 = 1.0 - c.mu - c.nu;
+    ajm1 = 1.0 - bj * Tj;
+    bjm2 = bjm1;
+    bjm1 = bj;
     Tm2 = Tm1; Tm1 = Tj;
     Dm2 = Dm1; Dm1 = Dj;
     Em2 = Em1; Em1 = Ej;
+    return c;
   }
-  w1 = Dm1 / Em1;
-}
+};
 
-// One RKC step of s stages from (y_n, F_n = f(y_n)) into y (Eqs. E:rkc0 - E:rkcs);
-// the coefficients b_j, mu_j, nu_j, mut_j, gt_j are formed stage by stage.
+// The coefficients for s <= kRkcTableS, evaluated by the compiler with the
+// same IEEE operations in the same order (no contraction), hence the same
+// bits as RkcCoef at run time; steps of up to kRkcTableS stages read them
+// instead of forming ten divisions per step.
+constexpr int kRkcTableS = 32;
+constexpr int rkc_table_row(int s) { return (s - 2) * (s - 1) / 2; }   // stage 2 of s
+struct RkcTable {
+  double mut1[kRkcTableS + 1];
+  RkcStageCoef st[rkc_table_row(kRkcTableS + 1)];
+};
+constexpr RkcTable make_rkc_table() {
+  RkcTable t{};
+  for (int s = 2; s <= kRkcTableS; ++s) {
+    RkcCoef c(s);
+    t.mut1[s] = c.mut1();
+    for (int j = 2; j <= s; ++j) t.st[rkc_table_row(s) + j - 2] = c.next();
+  }
+  return t;
+}
+inline constexpr RkcTable kRkcTable = make_rkc_table();
+
+// One RKC step of s stages from (y_n, F_n = f(y_n)) into y (Eqs. E:rkc0 - E:rkcs).
 template <class Prob, class Sink = NoSink>
 RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params& prm,
                       const Vec<Prob>& yn, const Vec<Prob>& Fn, double h, int s, Vec<Prob>& y,
                       double* slot, Sink* sink = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
-  double w0, w1;
-  rkc_omegas(s, w0, w1);
-  double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
-  double b2;
-  {
-    const double D2 = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-    const double E2 = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-    b2 = E2 / (D2 * D2);
-  }
-  double bjm1 = b2, bjm2 = b2;           // b_1 = b_0 = b_2
-  double ajm1 = 1.0 - bjm1 * w0;         // a_1 = 1 - b_1 T_1
+  const bool tab = s <= kRkcTableS;
+  RkcCoef cf(tab ? 2 : s);
+  const int row = tab ? rkc_table_row(s) - 2 : 0;
   Vec<Prob> wjm2 = work_vec<Prob>(slot, kCWm2), f = work_vec<Prob>(slot, kCFs);
-  const double mut1 = bjm1 * w1;
+  const double mut1 = tab ? kRkcTable.mut1[s] : cf.mut1();
   const double mh1 = mut1 * h;           // mut_1 h
   if (sink) sink->first(yn, mut1);
 #pragma unroll U
@@ -456,33 +510,19 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
     y[i] = yn[i] + mh1 * Fn[i];          // y holds w_{j-1}
   }
   for (int j = 2; j <= s; ++j) {
-    const double Tj = 2.0 * w0 * Tm1 - Tm2;
-    const double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-    const double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-    const double bj = Ej / (Dj * Dj);
-    const double mu = 2.0 * bj * w0 / bjm1;
-    const double nu = -bj / bjm2;
-    const double mut = 2.0 * bj * w1 / bjm1;
-    const double gt = -ajm1 * mut;
-    const double c0 = 1.0 - mu - nu;
-    const double mh = mut * h, gh = gt * h;
+    const RkcStageCoef k = tab ? kRkcTable.st[row + j] : cf.next();
+    const double mh = k.mut * h, gh = k.gt * h;
     if (sink) {
-      sink->stage(j, y, mu, nu, mut, gt);
+      sink->stage(j, y, k.mu, k.nu, k.mut, k.gt);
       if (Sink::kStopAtLast && j == s) return;
     }
     eval_rhs<Prob>(L, prm, y, f);
 #pragma unroll U
     for (int i = 0; i < N; ++i) {
-      const double wj = c0 * yn[i] + mu * y[i] + nu * wjm2[i] + mh * f[i] + gh * Fn[i];
+      const double wj = k.c0 * yn[i] + k.mu * y[i] + k.nu * wjm2[i] + mh * f[i] + gh * Fn[i];
       wjm2[i] = y[i];
       y[i] = wj;
     }
-    ajm1 = 1.0 - bj * Tj;
-    bjm2 = bjm1;
-    bjm1 = bj;
-    Tm2 = Tm1; Tm1 = Tj;
-    Dm2 = Dm1; Dm1 = Dj;
-    Em2 = Em1; Em1 = Ej;
   }
 }
 
@@ -705,16 +745,17 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     S.t += S.h;
     ++S.nstep;
     ++S.n_acc;
-    // err^(1/3) and err^(2/3) share one logarithm; err^(1/3) is kept for the
-    // next accepted step, where it is err_prev^(1/3)
-    const crm::dd lerr = crm::log_of_nonneg(err);
-    const double cbrt_err = crm::pow_from_log_nonneg(err, lerr, 1.0 / 3.0);
+    // err^(1/3) is kept for the next accepted step, where it is err_prev^(1/3);
+    // err^(2/3) is the square of err^(1/3) (the double nearest 2/3 is twice
+    // the one nearest 1/3)
+    double cbrt_err, err23;
+    crm::pow_pair_from_log_unit(err, crm::log_of_nonneg(err), 1.0 / 3.0, cbrt_err, err23);
     double fac = 10.0;
     if (!S.have_prev) {
       if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
     } else {
       const double t1 = 0.8 * S.h * S.cbrt_err_prev;
-      const double t2 = S.h_prev * crm::pow_from_log_nonneg(err, lerr, 2.0 / 3.0);
+      const double t2 = S.h_prev * err23;
       if (t1 < fac * t2) fac = t1 / t2;
     }
     S.err_prev = err;

@@ -393,19 +393,11 @@ struct GRkc {
 
   // One RKC step of s stages from (yn, Fn) into y, as rkc_step.
   __device__ void step(const Grp<GP>& x, double hh, int s, double (&y)[S]) {
-    double w0, w1;
-    rkc_omegas(s, w0, w1);
-    double Tm2 = 1.0, Tm1 = w0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
-    double b2;
-    {
-      const double D2 = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-      const double E2 = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-      b2 = E2 / (D2 * D2);
-    }
-    double bjm1 = b2, bjm2 = b2;
-    double ajm1 = 1.0 - bjm1 * w0;
+    const bool tab = s <= kRkcTableS;
+    RkcCoef cf(tab ? 2 : s);
+    const int row = tab ? rkc_table_row(s) - 2 : 0;
     double wjm2[S], f[S];
-    const double mut1 = bjm1 * w1;
+    const double mut1 = tab ? kRkcTable.mut1[s] : cf.mut1();
     const double mh1 = mut1 * hh;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
@@ -413,29 +405,15 @@ struct GRkc {
       y[i] = yn[i] + mh1 * Fn[i];
     }
     for (int j = 2; j <= s; ++j) {
-      const double Tj = 2.0 * w0 * Tm1 - Tm2;
-      const double Dj = 2.0 * Tm1 + 2.0 * w0 * Dm1 - Dm2;
-      const double Ej = 4.0 * Dm1 + 2.0 * w0 * Em1 - Em2;
-      const double bj = Ej / (Dj * Dj);
-      const double mu = 2.0 * bj * w0 / bjm1;
-      const double nu = -bj / bjm2;
-      const double mut = 2.0 * bj * w1 / bjm1;
-      const double gt = -ajm1 * mut;
-      const double c0 = 1.0 - mu - nu;
-      const double mh = mut * hh, gh = gt * hh;
+      const RkcStageCoef k = tab ? kRkcTable.st[row + j] : cf.next();
+      const double mh = k.mut * hh, gh = k.gt * hh;
       group_rhs<GP>(L, x, y, f);
 #pragma unroll
       for (int i = 0; i < S; ++i) {
-        const double wj = c0 * yn[i] + mu * y[i] + nu * wjm2[i] + mh * f[i] + gh * Fn[i];
+        const double wj = k.c0 * yn[i] + k.mu * y[i] + k.nu * wjm2[i] + mh * f[i] + gh * Fn[i];
         wjm2[i] = y[i];
         y[i] = wj;
       }
-      ajm1 = 1.0 - bj * Tj;
-      bjm2 = bjm1;
-      bjm1 = bj;
-      Tm2 = Tm1; Tm1 = Tj;
-      Dm2 = Dm1; Dm1 = Dj;
-      Em2 = Em1; Em1 = Ej;
     }
   }
 
@@ -507,14 +485,14 @@ struct GRkc {
       t += h;
       ++nstep;
       ++n_acc;
-      const crm::dd lerr = crm::log_of_nonneg(err);
-      const double cbrt_err = crm::pow_from_log_nonneg(err, lerr, 1.0 / 3.0);
+      double cbrt_err, err23;
+      crm::pow_pair_from_log_unit(err, crm::log_of_nonneg(err), 1.0 / 3.0, cbrt_err, err23);
       double fac = 10.0;
       if (!have_prev) {
         if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
       } else {
         const double t1 = 0.8 * h * cbrt_err_prev;
-        const double t2 = h_prev * crm::pow_from_log_nonneg(err, lerr, 2.0 / 3.0);
+        const double t2 = h_prev * err23;
         if (t1 < fac * t2) fac = t1 / t2;
       }
       err_prev = err;

@@ -209,10 +209,11 @@ def kinetics_inputs(net: Network, n: int, seed: int, T_range=(1000.0, 2500.0), r
     return Y, g
 
 
-def vdp_inputs(n: int, seed: int):
-    """(y0 [2, n], g [1, n]): mu ~ U[0.5, 2], y0 ~ U[-2, 2]^2."""
+def vdp_inputs(n: int, seed: int, mu_range=(0.5, 2.0)):
+    """(y0 [2, n], g [1, n]): mu ~ U[mu_range] (default [0.5, 2]; [300, 3000] is
+    stiff: RKC steps of 10 to 60 stages), y0 ~ U[-2, 2]^2."""
     rng = np.random.default_rng(seed)
-    mu = rng.uniform(0.5, 2.0, n)
+    mu = rng.uniform(mu_range[0], mu_range[1], n)
     y0 = rng.uniform(-2.0, 2.0, (2, n))
     return np.ascontiguousarray(y0), np.ascontiguousarray(mu[None, :])
 

@@ -99,6 +99,24 @@ def test_kernel_math_matches_oracle_bulk(orc):
                               np.array([orc.cr_pow(v, y) for v in x]))
 
 
+def test_kernel_pow_pair_is_correctly_rounded(orc):
+    """The RKC controller's err^(1/3) and err^(2/3) from one exp (the second as
+    the double-double square of the first) are the correctly rounded powers."""
+    run = _kernel_math()
+    rng = np.random.default_rng(5)
+    x = np.concatenate([10 ** rng.uniform(-300, 0, 3000), rng.uniform(0, 1, 3000),
+                        1.0 - 10 ** rng.uniform(-16, -3, 500),
+                        [0.0, 1.0, 5e-324, 2.0 ** -1022, 2.0 ** -1074 * 3, 0.5, 0.999999]])
+    y = np.full(x.size, 1.0 / 3.0)
+    p1, p2 = run(3, x, y), run(4, x, y)
+    assert p1.tolist() == [_cr(mp.power(mp.mpf(float(v)), mp.mpf(1.0 / 3.0))) for v in x]
+    assert p2.tolist() == [_cr(mp.power(mp.mpf(float(v)), mp.mpf(2.0 / 3.0))) for v in x]
+    xb = rng.uniform(0, 1, 100_000)
+    yb = np.full(xb.size, 1.0 / 3.0)
+    assert np.array_equal(run(3, xb, yb), np.array([orc.cr_pow(v, 1.0 / 3.0) for v in xb]))
+    assert np.array_equal(run(4, xb, yb), np.array([orc.cr_pow(v, 2.0 / 3.0) for v in xb]))
+
+
 def test_kernel_math_special_values():
     run = _kernel_math()
     inf, nan = float("inf"), float("nan")

@@ -36,8 +36,8 @@ def _orc(orc, method, pb, y0, g, t0, t1, rtol, atol, **kw):
 
 def _case(rk, orc, method, problem, n, seed, t0, t1, rtol, atol, T_range=(1000.0, 2500.0), **kw):
     say(f"case {method} {problem} n={n} seed={seed} t=[{t0},{t1}] rtol={rtol} atol={atol}")
-    if problem == "vdp":
-        y0, g = I.vdp_inputs(n, seed)
+    if problem in ("vdp", "vdp_stiff"):
+        y0, g = I.vdp_inputs(n, seed, (300.0, 3000.0) if problem == "vdp_stiff" else (0.5, 2.0))
         prob, pb = rk.Problem.vdp(), orc.vdp()
     else:
         net = I.network_of(problem)
@@ -69,6 +69,13 @@ def test_net9_rkc(rk, orc):
 
 def test_net13_rkck(rk, orc):
     _case(rk, orc, "rkck", "net13", 700, 12, 0.0, 2e-8, 1e-8, 1e-12)
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+def test_vdp_rkc_stiff_many_stages(rk, orc, schedule):
+    """Steps of 10 to 60 stages: lanes of a wave read tabulated coefficients
+    (up to 32 stages) or form them, side by side."""
+    _case(rk, orc, "rkc", "vdp_stiff", 1000, 13, 0.0, 1.0, 1e-6, 1e-8, schedule=schedule)
 
 
 def test_vdp_rkck_loose_and_tight(rk, orc):
@@ -184,8 +191,10 @@ def test_device_math_equals_host_and_oracle(rk, orc):
     cases = [(0, rng.uniform(-45, 45, n), np.zeros(n)),
              (1, rng.uniform(300, 4000, n), np.zeros(n)),
              (2, 10 ** rng.uniform(-20, 3, n), np.full(n, -0.2)),
-             (2, 10 ** rng.uniform(-20, 3, n), np.full(n, 2.0 / 3.0))]
-    ref = {0: orc.cr_exp, 1: orc.cr_log}
+             (2, 10 ** rng.uniform(-20, 3, n), np.full(n, 2.0 / 3.0)),
+             (3, rng.uniform(0, 1, n), np.full(n, 1.0 / 3.0)),
+             (4, rng.uniform(0, 1, n), np.full(n, 1.0 / 3.0))]
+    ref = {0: orc.cr_exp, 1: orc.cr_log, 3: orc.cr_pow, 4: lambda v, w: orc.cr_pow(v, 2 * w)}
     for fn, x, y in cases:
         xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
         od = torch.empty_like(xd)
@@ -196,7 +205,8 @@ def test_device_math_equals_host_and_oracle(rk, orc):
         dev = od.cpu().numpy()
         assert np.array_equal(dev, oh), (fn, int((dev != oh).sum()))
         m = 20000
-        r = np.array([ref[fn](v) if fn < 2 else orc.cr_pow(v, w) for v, w in zip(x[:m], y[:m])])
+        r = np.array([ref[fn](v) if fn < 2 else ref.get(fn, orc.cr_pow)(v, w)
+                      for v, w in zip(x[:m], y[:m])])
         assert np.array_equal(dev[:m], r)
 
 

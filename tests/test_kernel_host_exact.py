@@ -34,6 +34,8 @@ def _host_run(prob, method, y0, g, t0, t1, rtol, atol, max_steps=0):
 CASES = [
     ("rkck", "vdp", 200, 1, 0.0, 10.0, 1e-8, 1e-10, None),
     ("rkc", "vdp", 120, 3, 0.0, 2.0, 1e-8, 1e-10, None),
+    # stiff: steps of up to and beyond 32 stages (tabulated and formed coefficients)
+    ("rkc", "vdp_stiff", 48, 13, 0.0, 1.0, 1e-6, 1e-8, None),
     ("rkc", "net9", 96, 77, 0.0, 1e-6, 1e-8, 1e-12, (800.0, 3000.0)),
     ("rkc", "net13", 96, 2002, 0.0, 1e-6, 1e-8, 1e-12, (1000.0, 2500.0)),
     ("rkck", "net13", 32, 12, 0.0, 2e-8, 1e-8, 1e-12, (1000.0, 2500.0)),
@@ -58,8 +60,8 @@ CASES = [
 def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, t1, rtol, atol,
                                              T_range):
     import paper_1611_02274_amd as rk
-    if problem == "vdp":
-        y0, g = I.vdp_inputs(n, seed)
+    if problem in ("vdp", "vdp_stiff"):
+        y0, g = I.vdp_inputs(n, seed, (300.0, 3000.0) if problem == "vdp_stiff" else (0.5, 2.0))
         prob, pb = rk.Problem.vdp(), orc.vdp()
     elif problem == "pleiades":
         y0, g = I.pleiades_inputs(n, seed)
@@ -78,6 +80,8 @@ def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, 
     assert np.array_equal(sh, so)
     assert np.array_equal(sth, sto), np.argwhere(sth != sto)[:5]
     assert np.array_equal(yh.view(np.int64), yo.view(np.int64))
+    if problem == "vdp_stiff":
+        assert sto[5].min() <= 32 < sto[5].max()
 
 
 def test_host_build_max_steps(orc):
