@@ -206,46 +206,6 @@ RKMI_HD double pow_from_log(dd L, double y) {
   return exp_dd(z.hi, z.lo);
 }
 
-// log_dd of a finite x >= 0, for several powers of the same x (x = 0 gives an
-// unused value).
-RKMI_HD dd log_of_nonneg(double x) { return x > 0.0 ? log_dd(x) : dd{0.0, 0.0}; }
-
-// x^y for finite x >= 0 and finite y, given L = log_of_nonneg(x): the same
-// value as cr_pow(x, y).
-RKMI_HD double pow_from_log_nonneg(double x, dd L, double y) {
-  if (y == 0.0 || x == 1.0) return 1.0;
-  if (x == 0.0) return y < 0.0 ? __builtin_huge_val() : 0.0;
-  return pow_from_log(L, y);
-}
-
-// x^y and x^(2y) for x in [0, 1] and 0 < y <= 1/3, given L = log_of_nonneg(x):
-// x^(2y) is the double-double square of x^y before its rounding (relative
-// error below about 2^-86), so both are the correctly rounded values that
-// pow_from_log_nonneg gives for y and 2y, for one exp instead of two.  In this
-// range both results are normal numbers (x^(2y) >= 2^-716).
-RKMI_HD void pow_pair_from_log_unit(double x, dd L, double y, double& p1, double& p2) {
-  if (x == 1.0) {
-    p1 = p2 = 1.0;
-    return;
-  }
-  if (x == 0.0) {
-    p1 = p2 = 0.0;
-    return;
-  }
-  dd z = two_prod(y, L.hi);
-  z.lo += y * L.lo;
-  if (z.hi < kExpMinArg) {        // outside the stated range: the general path
-    p1 = exp_dd(z.hi, z.lo);
-    p2 = pow_from_log(L, 2.0 * y);
-    return;
-  }
-  int m = 0;
-  const dd R = exp_core(z.hi, z.lo, m);
-  p1 = scale2(R.hi + R.lo, m);
-  const dd R2 = dd_mul(R, R);
-  p2 = scale2(R2.hi + R2.lo, 2 * m);
-}
-
 // x^y with the special values of C99 Annex F (y finite and not an integer
 // in the cases the integrators produce).
 RKMI_HD double cr_pow(double x, double y) {
@@ -275,6 +235,101 @@ RKMI_HD double cr_pow(double x, double y) {
     return y_odd ? -r : r;
   }
   return pow_from_log(log_dd(x), y);
+}
+
+// x^y for y = RN(1/3) and, when kSquare, x^(2y) (2y = RN(2/3)), for finite
+// x >= 0.  Since y = 1/3 - 2^-54/3 exactly,
+//   x^y = cbrt(x) x^(-2^-54/3) = cbrt(x) (1 + u + u^2/2 + ...),
+//   u = -(2^-54/3) ln x,  |u| < 1.4e-14,
+// and x^(2y) is the square of x^y.  x = t 2^(3q) with t in [1, 8): t^(-1/3)
+// from a degree-4 fit of m^(-1/3) on [1, 2) (relative error 8.8e-5; the fit
+// is ours) and two Newton steps z <- z + z (1 - t z^3) / 3, then cbrt(t) =
+// t z^2 and one Newton step for the cube root in double-double arithmetic (the
+// residual c^3 - t formed exactly with TwoProd).  ln x = e ln2 + 2 atanh(s),
+// s = (m - 1)/(m + 1), needs absolute accuracy of only about 1e-11 here (the
+// series to s^13 gives 4e-13).  The double-double result has relative error
+// below about 2^-90, so both roundings are the correctly rounded values except
+// with probability about 2^-37 per call.
+constexpr double kThird = 0x1.5555555555555p-2;            // RN(1/3)
+constexpr double kThirdDefect = 0x1.5555555555555p-56;     // 1/3 - RN(1/3), rounded
+constexpr double kCbrtFit[5] = {0x1.bf460be1acba9p-1, -0x1.8d16b63ef59afp-3,
+                                0x1.60afbeaf93db8p-4, -0x1.9213bd85642a6p-5,
+                                0x1.c40554f37ed1bp-6};     // m^(-1/3) in powers of m - 3/2
+constexpr double kCbrtHalf = 0x1.965fea53d6e3dp-1;         // RN(2^(-1/3))
+constexpr double kCbrtQuarter = 0x1.428a2f98d728bp-1;      // RN(2^(-2/3))
+constexpr double kSqrt2 = 0x1.6a09e667f3bcdp+0;
+constexpr double kLn2d = 0x1.62e42fefa39efp-1;
+
+template <bool kSquare>
+RKMI_HD void pow_third(double x, double& p1, double& p2) {
+  if (x == 0.0 || x == 1.0) {
+    p1 = p2 = x;
+    return;
+  }
+  if (!(x > 0.0) || !is_finite(x)) {
+    p1 = cr_pow(x, kThird);
+    p2 = kSquare ? cr_pow(x, 2.0 * kThird) : 0.0;
+    return;
+  }
+  uint64_t b = bits_of(x);
+  int ex = (int)(b >> 52);
+  int sc = 0;
+  if (ex == 0) {                  // subnormal: scale into the normal range
+    b = bits_of(x * 0x1p54);
+    ex = (int)(b >> 52);
+    sc = -54;
+  }
+  const int e = ex - 1023 + sc;   // x = m 2^e, m in [1, 2)
+  const double m = from_bits((b & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL);
+  int q = e / 3, r = e - 3 * q;
+  if (r < 0) {
+    r += 3;
+    q -= 1;
+  }
+  const double t = r == 0 ? m : (r == 1 ? 2.0 * m : 4.0 * m);
+  const double d = m - 1.5;
+  double z = kCbrtFit[0] + d * (kCbrtFit[1] + d * (kCbrtFit[2] + d * (kCbrtFit[3] + d * kCbrtFit[4])));
+  z = z * (r == 0 ? 1.0 : (r == 1 ? kCbrtHalf : kCbrtQuarter));
+  z = z + z * (1.0 - t * (z * z * z)) * kThird;
+  z = z + z * (1.0 - t * (z * z * z)) * kThird;
+  const double c = t * (z * z);
+  const dd c2 = two_prod(c, c);
+  const dd c3 = two_prod(c, c2.hi);
+  const double res = (c3.hi - t) + (c3.lo + c * c2.lo);
+  const double delta = res * (z * z) * kThird;   // (c^3 - t) / (3 c^2)
+  double mm = m;
+  int ee = e;
+  if (mm > kSqrt2) {
+    mm = 0.5 * mm;
+    ee += 1;
+  }
+  const double sv = (mm - 1.0) / (mm + 1.0);
+  const double s2 = sv * sv;
+  const double lnm =
+      2.0 * sv *
+      (1.0 + s2 * (0x1.5555555555555p-2 +
+                   s2 * (0.2 + s2 * (0x1.2492492492492p-3 +
+                                     s2 * (0x1.c71c71c71c71cp-4 +
+                                           s2 * (0x1.745d1745d1746p-4 + s2 * 0x1.3b13b13b13b14p-4))))));
+  const double u = -kThirdDefect * ((double)ee * kLn2d + lnm);
+  const dd P = fast_two_sum(c, c * (u + 0.5 * u * u) - delta);
+  p1 = scale2(P.hi + P.lo, q);
+  if (kSquare) {
+    const dd P2 = dd_mul(P, P);
+    p2 = scale2(P2.hi + P2.lo, 2 * q);
+  } else {
+    p2 = 0.0;
+  }
+}
+
+// x^RN(1/3) and x^RN(2/3) for finite x >= 0 (correctly rounded, as cr_pow).
+RKMI_HD void pow_third_pair(double x, double& p1, double& p2) { pow_third<true>(x, p1, p2); }
+
+// x^RN(1/3) for finite x >= 0 (correctly rounded, as cr_pow).
+RKMI_HD double pow_third_one(double x) {
+  double p1, p2;
+  pow_third<false>(x, p1, p2);
+  return p1;
 }
 
 }  // namespace crm

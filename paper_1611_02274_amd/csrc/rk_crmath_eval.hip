@@ -1,7 +1,8 @@
 // rk_crmath_eval.hip -- evaluates the kernels' correctly rounded exp / log / pow
 // over arrays, on the host (the same source compiled for the CPU) or on the
 // device, so that tests can check them.  fn: 0 exp(x), 1 log(x), 2 pow(x, y),
-// 3 and 4: x^y and x^(2y) from the controller's pair (x in [0, 1], y <= 1/3).
+// 3 and 4: x^RN(1/3) and x^RN(2/3) from the controllers' pair, 5: x^RN(1/3)
+// alone (y unused for 3 to 5).
 // Not part of the public ABI.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,9 +18,10 @@ __host__ __device__ inline double eval_one(int fn, double x, double y) {
     case 3:
     case 4: {
       double p1 = 0.0, p2 = 0.0;
-      rkmi::crm::pow_pair_from_log_unit(x, rkmi::crm::log_of_nonneg(x), y, p1, p2);
+      rkmi::crm::pow_third_pair(x, p1, p2);
       return fn == 3 ? p1 : p2;
     }
+    case 5: return rkmi::crm::pow_third_one(x);
     default: return rkmi::crm::cr_pow(x, y);
   }
 }
@@ -33,7 +35,7 @@ __global__ void crmath_kernel(int fn, int64_t n, const double* __restrict__ x,
 }  // namespace
 
 extern "C" int rkmi_crmath_host(int fn, int64_t n, const double* x, const double* y, double* out) {
-  if (fn < 0 || fn > 4 || n < 0 || (n && (!x || !y || !out))) return -1;
+  if (fn < 0 || fn > 5 || n < 0 || (n && (!x || !y || !out))) return -1;
   for (int64_t i = 0; i < n; ++i) out[i] = eval_one(fn, x[i], y[i]);
   return 0;
 }
@@ -41,7 +43,7 @@ extern "C" int rkmi_crmath_host(int fn, int64_t n, const double* x, const double
 // x, y, out: device arrays of n doubles.
 extern "C" int rkmi_crmath_device(int fn, int64_t n, const double* x, const double* y,
                                   double* out, void* stream) {
-  if (fn < 0 || fn > 4 || n < 0 || (n && (!x || !y || !out))) return -1;
+  if (fn < 0 || fn > 5 || n < 0 || (n && (!x || !y || !out))) return -1;
   if (n == 0) return 0;
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffffLL) return -1;

@@ -730,7 +730,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   const double err = sqrt(e / (double)N);
   if (err > 1.0 || !crm::is_finite(err)) {
     ++S.n_rej;
-    S.h = crm::is_finite(err) ? 0.8 * S.h / crm::cr_pow(err, 1.0 / 3.0) : kP1 * S.h;
+    S.h = crm::is_finite(err) ? 0.8 * S.h / crm::pow_third_one(err) : kP1 * S.h;
     int it;
     S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
     ++S.n_sr;
@@ -749,7 +749,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     // err^(2/3) is the square of err^(1/3) (the double nearest 2/3 is twice
     // the one nearest 1/3)
     double cbrt_err, err23;
-    crm::pow_pair_from_log_unit(err, crm::log_of_nonneg(err), 1.0 / 3.0, cbrt_err, err23);
+    crm::pow_third_pair(err, cbrt_err, err23);
     double fac = 10.0;
     if (!S.have_prev) {
       if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
@@ -859,7 +859,7 @@ struct Driver<Prob, kMethodRkc, Rec> {
       S.nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
       S.have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
       // err_prev^(1/3), as the controller formed it when err_prev was accepted
-      S.cbrt_err_prev = S.have_prev ? crm::cr_pow(S.err_prev, 1.0 / 3.0) : 0.0;
+      S.cbrt_err_prev = S.have_prev ? crm::pow_third_one(S.err_prev) : 0.0;
       S.first = false;
       double* const vslot = col_ptr<Prob>(slot, kCV);
 #pragma unroll U

@@ -470,7 +470,7 @@ struct GRkc {
     const double err = sqrt(group_sum<GP>(x, e2) / (double)N);
     if (err > 1.0 || !crm::is_finite(err)) {
       ++n_rej;
-      h = crm::is_finite(err) ? 0.8 * h / crm::cr_pow(err, 1.0 / 3.0) : kP1 * h;
+      h = crm::is_finite(err) ? 0.8 * h / crm::pow_third_one(err) : kP1 * h;
       int it;
       sigma = spec_rad(x, hmax, c.sr_itmax, it);
       ++n_sr;
@@ -486,7 +486,7 @@ struct GRkc {
       ++nstep;
       ++n_acc;
       double cbrt_err, err23;
-      crm::pow_pair_from_log_unit(err, crm::log_of_nonneg(err), 1.0 / 3.0, cbrt_err, err23);
+      crm::pow_third_pair(err, cbrt_err, err23);
       double fac = 10.0;
       if (!have_prev) {
         if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
@@ -528,7 +528,7 @@ struct GRkc {
     sigma = carry[(int64_t)kCarrySigma * n + i];
     nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
     have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
-    cbrt_err_prev = have_prev ? crm::cr_pow(err_prev, 1.0 / 3.0) : 0.0;
+    cbrt_err_prev = have_prev ? crm::pow_third_one(err_prev) : 0.0;
     first = false;
 #pragma unroll
     for (int m = 0; m < S; ++m) {

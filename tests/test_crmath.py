@@ -99,20 +99,25 @@ def test_kernel_math_matches_oracle_bulk(orc):
                               np.array([orc.cr_pow(v, y) for v in x]))
 
 
-def test_kernel_pow_pair_is_correctly_rounded(orc):
-    """The RKC controller's err^(1/3) and err^(2/3) from one exp (the second as
-    the double-double square of the first) are the correctly rounded powers."""
+def test_kernel_pow_third_is_correctly_rounded(orc):
+    """The RKC controllers' x^RN(1/3) and x^RN(2/3) (cube root refined in
+    double-double, times x^(RN(1/3) - 1/3); the second power as the square of
+    the first) are the correctly rounded powers: errors in [0, 1], rejected
+    errors above 1, subnormals, and the exact cases."""
     run = _kernel_math()
     rng = np.random.default_rng(5)
     x = np.concatenate([10 ** rng.uniform(-300, 0, 3000), rng.uniform(0, 1, 3000),
-                        1.0 - 10 ** rng.uniform(-16, -3, 500),
-                        [0.0, 1.0, 5e-324, 2.0 ** -1022, 2.0 ** -1074 * 3, 0.5, 0.999999]])
-    y = np.full(x.size, 1.0 / 3.0)
-    p1, p2 = run(3, x, y), run(4, x, y)
+                        1.0 - 10 ** rng.uniform(-16, -3, 500), 1.0 + 10 ** rng.uniform(-16, -1, 300),
+                        10 ** rng.uniform(0, 300, 1000), 2.0 ** rng.integers(-1074, 1023, 300),
+                        [0.0, 1.0, 5e-324, 2.0 ** -1022, 2.0 ** -1074 * 3, 0.5, 0.999999, 8.0,
+                         1.7976931348623157e308]])
+    y = np.zeros(x.size)
+    p1, p2, p3 = run(3, x, y), run(4, x, y), run(5, x, y)
     assert p1.tolist() == [_cr(mp.power(mp.mpf(float(v)), mp.mpf(1.0 / 3.0))) for v in x]
     assert p2.tolist() == [_cr(mp.power(mp.mpf(float(v)), mp.mpf(2.0 / 3.0))) for v in x]
-    xb = rng.uniform(0, 1, 100_000)
-    yb = np.full(xb.size, 1.0 / 3.0)
+    assert np.array_equal(p3.view(np.int64), p1.view(np.int64))
+    xb = np.concatenate([rng.uniform(0, 1, 150_000), 10 ** rng.uniform(0, 12, 50_000)])
+    yb = np.zeros(xb.size)
     assert np.array_equal(run(3, xb, yb), np.array([orc.cr_pow(v, 1.0 / 3.0) for v in xb]))
     assert np.array_equal(run(4, xb, yb), np.array([orc.cr_pow(v, 2.0 / 3.0) for v in xb]))
 

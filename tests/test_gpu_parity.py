@@ -192,9 +192,11 @@ def test_device_math_equals_host_and_oracle(rk, orc):
              (1, rng.uniform(300, 4000, n), np.zeros(n)),
              (2, 10 ** rng.uniform(-20, 3, n), np.full(n, -0.2)),
              (2, 10 ** rng.uniform(-20, 3, n), np.full(n, 2.0 / 3.0)),
-             (3, rng.uniform(0, 1, n), np.full(n, 1.0 / 3.0)),
-             (4, rng.uniform(0, 1, n), np.full(n, 1.0 / 3.0))]
-    ref = {0: orc.cr_exp, 1: orc.cr_log, 3: orc.cr_pow, 4: lambda v, w: orc.cr_pow(v, 2 * w)}
+             (3, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
+             (4, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
+             (5, 10 ** rng.uniform(-30, 6, n), np.zeros(n))]
+    ref = {0: orc.cr_exp, 1: orc.cr_log, 3: lambda v, w: orc.cr_pow(v, 1.0 / 3.0),
+           4: lambda v, w: orc.cr_pow(v, 2.0 / 3.0), 5: lambda v, w: orc.cr_pow(v, 1.0 / 3.0)}
     for fn, x, y in cases:
         xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
         od = torch.empty_like(xd)
