@@ -392,7 +392,7 @@ def main():
                   3: "group (several lanes per system, groups refilled from a device queue)"
                   }[launch.get("schedule", 0)]
     if launch.get("cost_order"):
-        sched_name += ("; cost order (a pilot at 1e4 x looser tolerances counts each system's "
+        sched_name += ("; cost order (a pilot at tolerances loosened 1e5 x, rtol at most 1e-3, counts each system's "
                        "steps, systems handed out in decreasing count; pilot and sort inside "
                        "the timed step)")
 

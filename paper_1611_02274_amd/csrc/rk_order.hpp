@@ -37,9 +37,9 @@ constexpr int kOrderPerThread = kOrderBuckets / kOrderScanThreads;
 // system after kPilotMaxAttempts attempts: the costliest systems then share
 // the top bucket (they start first either way), and no wave of the pilot
 // waits long for one slow system.
-constexpr double kPilotLoosen = 1.0e4;
+constexpr double kPilotLoosen = 1.0e5;
 constexpr double kPilotRtolMax = 1.0e-3;
-constexpr int64_t kPilotMaxAttempts = 192;
+constexpr int64_t kPilotMaxAttempts = 128;
 
 constexpr size_t order_align(size_t b) { return (b + 255) / 256 * 256; }
 
