@@ -75,6 +75,8 @@ struct TapeRec {
   TapeView T;
   int64_t i;
   bool full;
+  int32_t phase = 0;     // accepted steps since the last checkpoint (nstep mod K)
+  int64_t ck = 0;        // checkpoints written (nstep / K)
   template <class V>
   RKMI_HD void checkpoint(int64_t c, const V& y) {
 #pragma unroll
@@ -89,7 +91,10 @@ struct TapeRec {
     }
     T.h[k * T.n + i] = h;
     T.s[k * T.n + i] = m;
-    if (nstep % T.K == 0) checkpoint(nstep / T.K, yn);
+    if (++phase == T.K) {          // nstep % K == 0: checkpoint nstep / K
+      phase = 0;
+      checkpoint(++ck, yn);
+    }
   }
 };
 

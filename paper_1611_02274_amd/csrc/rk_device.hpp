@@ -428,6 +428,7 @@ struct RkcCoef {
   double Tm2 = 1.0, Tm1 = 0.0, Dm2 = 0.0, Dm1 = 1.0, Em2 = 0.0, Em1 = 0.0;
   double bjm1 = 0.0, bjm2 = 0.0, ajm1 = 0.0;
 
+  constexpr __host__ __device__ RkcCoef() {}     // unset (tabulated stage counts)
   constexpr __host__ __device__ explicit RkcCoef(int s) {
     w0 = 1.0 + kKappa / ((double)s * (double)s);
     double tm2 = 1.0, tm1 = w0, dm2 = 0.0, dm1 = 1.0, em2 = 0.0, em1 = 0.0;
@@ -498,7 +499,8 @@ RKMI_HD void rkc_step(const typename Prob::Lane& L, const typename Prob::Params&
                       double* slot, Sink* sink = nullptr) {
   constexpr int N = Prob::N, U = kUnroll<Prob>;
   const bool tab = s <= kRkcTableS;
-  RkcCoef cf(tab ? 2 : s);
+  RkcCoef cf;
+  if (!tab) cf = RkcCoef(s);
   const int row = tab ? rkc_table_row(s) - 2 : 0;
   Vec<Prob> wjm2 = work_vec<Prob>(slot, kCWm2), f = work_vec<Prob>(slot, kCFs);
   const double mut1 = tab ? kRkcTable.mut1[s] : cf.mut1();
@@ -626,6 +628,7 @@ struct RkcState {
   double t, h, h_prev, err_prev, sigma;
   double cbrt_err_prev;      // err_prev^(1/3), formed when err_prev was accepted
   int64_t nstep, attempts;
+  int32_t sr_phase;          // nstep mod sr_period, kept step by step (no 64-bit modulo)
   int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
   bool first, have_prev;
   double h_want;   // the step before the cut to the interval end
@@ -666,6 +669,7 @@ RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params
   S.h_want = 0.0;
   S.cut = false;
   S.nstep = 0;
+  S.sr_phase = 0;
   S.first = true;
   S.have_prev = false;
 }
@@ -683,7 +687,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   }
   S.h_want = S.h;
   if (1.1 * S.h >= fabs(c.t1 - S.t)) S.h = fabs(c.t1 - S.t);
-  if (S.nstep % c.sr_period == 0) {
+  if (S.sr_phase == 0) {          // nstep % sr_period == 0
     int it;
     S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
     ++S.n_sr;
@@ -744,6 +748,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
     S.cut = S.h < S.h_want;
     S.t += S.h;
     ++S.nstep;
+    if (++S.sr_phase == c.sr_period) S.sr_phase = 0;
     ++S.n_acc;
     // err^(1/3) is kept for the next accepted step, where it is err_prev^(1/3);
     // err^(2/3) is the square of err^(1/3) (the double nearest 2/3 is twice
@@ -857,6 +862,7 @@ struct Driver<Prob, kMethodRkc, Rec> {
       S.err_prev = carry[(int64_t)kCarryErrPrev * n + i];
       S.sigma = carry[(int64_t)kCarrySigma * n + i];
       S.nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
+      S.sr_phase = (int32_t)(S.nstep % c.sr_period);
       S.have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
       // err_prev^(1/3), as the controller formed it when err_prev was accepted
       S.cbrt_err_prev = S.have_prev ? crm::pow_third_one(S.err_prev) : 0.0;

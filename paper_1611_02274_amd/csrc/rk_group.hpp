@@ -286,7 +286,8 @@ struct GRkck {
   __device__ const double (&state() const)[S] { return y; }
   __device__ double (&state())[S] { return y; }
   // carried controller state (rows of the carry array), as the one-lane driver
-  __device__ void load_carry(const Grp<GP>&, const double* carry, int64_t n, int64_t i) {
+  __device__ void load_carry(const Grp<GP>&, const Ctl&, const double* carry, int64_t n,
+                             int64_t i) {
     h = carry[(int64_t)kCarryH * n + i];
     h_want = h;
   }
@@ -305,6 +306,7 @@ struct GRkc {
   double yn[S], Fn[S], v[S];
   double t, h, h_prev, err_prev, sigma, cbrt_err_prev, h_want;
   int64_t nstep, attempts;
+  int32_t sr_phase;          // nstep mod sr_period
   int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
   bool first, have_prev, cut;
 
@@ -323,6 +325,7 @@ struct GRkc {
     gcopy<GP>(v, Fn);
     h = h_prev = err_prev = sigma = cbrt_err_prev = h_want = 0.0;
     nstep = 0;
+    sr_phase = 0;
     first = true;
     have_prev = false;
     cut = false;
@@ -394,7 +397,8 @@ struct GRkc {
   // One RKC step of s stages from (yn, Fn) into y, as rkc_step.
   __device__ void step(const Grp<GP>& x, double hh, int s, double (&y)[S]) {
     const bool tab = s <= kRkcTableS;
-    RkcCoef cf(tab ? 2 : s);
+    RkcCoef cf;
+    if (!tab) cf = RkcCoef(s);
     const int row = tab ? rkc_table_row(s) - 2 : 0;
     double wjm2[S], f[S];
     const double mut1 = tab ? kRkcTable.mut1[s] : cf.mut1();
@@ -425,7 +429,7 @@ struct GRkc {
     }
     h_want = h;
     if (1.1 * h >= fabs(c.t1 - t)) h = fabs(c.t1 - t);
-    if (nstep % c.sr_period == 0) {
+    if (sr_phase == 0) {
       int it;
       sigma = spec_rad(x, hmax, c.sr_itmax, it);
       ++n_sr;
@@ -484,6 +488,7 @@ struct GRkc {
       cut = h < h_want;
       t += h;
       ++nstep;
+      if (++sr_phase == c.sr_period) sr_phase = 0;
       ++n_acc;
       double cbrt_err, err23;
       crm::pow_third_pair(err, cbrt_err, err23);
@@ -521,12 +526,14 @@ struct GRkc {
   }
   __device__ const double (&state() const)[S] { return yn; }
   __device__ double (&state())[S] { return yn; }
-  __device__ void load_carry(const Grp<GP>& x, const double* carry, int64_t n, int64_t i) {
+  __device__ void load_carry(const Grp<GP>& x, const Ctl& c, const double* carry, int64_t n,
+                             int64_t i) {
     h = carry[(int64_t)kCarryH * n + i];
     h_prev = carry[(int64_t)kCarryHPrev * n + i];
     err_prev = carry[(int64_t)kCarryErrPrev * n + i];
     sigma = carry[(int64_t)kCarrySigma * n + i];
     nstep = (int64_t)carry[(int64_t)kCarryNstep * n + i];
+    sr_phase = (int32_t)(nstep % c.sr_period);
     have_prev = carry[(int64_t)kCarryHavePrev * n + i] != 0.0;
     cbrt_err_prev = have_prev ? crm::pow_third_one(err_prev) : 0.0;
     first = false;
@@ -574,7 +581,7 @@ struct GDriver {
       D.begin(c);
     else
       D.begin(x, c);
-    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) D.load_carry(x, carry, n, i);
+    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) D.load_carry(x, c, carry, n, i);
     return D.t < c.t1;
   }
   __device__ bool attempt(const Ctl& c, const Grp<GP>& x) { return D.attempt(x, c); }
