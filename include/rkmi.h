@@ -122,9 +122,12 @@ int rk_problem_create_vdp(rk_problem *out);
  *   x_i'' = sum_{j != i} m_j (x_j - x_i) / r_ij,  y_i'' likewise,
  *   r_ij = ((x_i - x_j)^2 + (y_i - y_j)^2)^(3/2),
  * the 3/2 power formed as d2 sqrt(d2) and the division as a multiplication by
- * the pair's reciprocal.  No per-system parameters (pass g = NULL).  Its
- * vectors live in workspace columns: every schedule needs rk_workspace_bytes.
- * No adjoint (RK_EUNSUPPORTED). */
+ * the pair's reciprocal.  No per-system parameters (pass g = NULL).  The
+ * group schedule (the default, RK_SCHED_AUTO) spreads a system over eight
+ * lanes with its vectors in registers; the plain and persistent schedules run
+ * one lane per system with its vectors in workspace columns.  Every schedule
+ * needs rk_workspace_bytes (the group one for its queue).  All schedules give
+ * the same bits.  No adjoint (RK_EUNSUPPORTED). */
 int rk_problem_create_pleiades(rk_problem *out);
 
 /* Mass-action network described by *desc (host memory, copied).  The network

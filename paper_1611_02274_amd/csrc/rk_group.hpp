@@ -104,10 +104,36 @@ __device__ bool group_all_finite(const Grp<GP>& x, const double (&y)[GP::S]) {
   return !group_any(x, bad);
 }
 
+// A group problem with a right-hand side of its own (GP::kOwnRhs, GP::rhs)
+// rather than the mass-action exchange below.
+template <class GP, class = void>
+struct GroupOwnRhs {
+  static constexpr bool value = false;
+};
+template <class GP>
+struct GroupOwnRhs<GP, std::void_t<decltype(GP::kOwnRhs)>> {
+  static constexpr bool value = GP::kOwnRhs;
+};
+
+template <class GP>
+__device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>& x,
+                                      const double (&y)[GP::S], double (&f)[GP::S]);
+
 // Right-hand side of the group's system at y (owned slots) into f.
 template <class GP>
 __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const double (&y)[GP::S],
                           double (&f)[GP::S]) {
+  if constexpr (GroupOwnRhs<GP>::value)
+    GP::rhs(L, x, y, f);
+  else
+    group_rhs_mass_action<GP>(L, x, y, f);
+}
+
+// Mass action: concentrations, [M] and rates of progress exchanged through
+// the group's LDS area (the scheme in the header comment).
+template <class GP>
+__device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>& x,
+                                      const double (&y)[GP::S], double (&f)[GP::S]) {
   constexpr int N = GP::N, NR = GP::NR, LL = GP::kL;
   (void)LL;
   double* const C = x.lds + GP::kOffC;

@@ -8,8 +8,11 @@
 // pair's value is the same bits for (i, j) and (j, i): the squared differences
 // of negated operands are equal).  Each body's sums run over j in increasing
 // order from zero.  Its 28-vectors are too many for registers in the RKCK
-// driver, so they live in the lane's workspace columns (the column tier).
+// driver: one lane per system keeps them in workspace columns (the column
+// tier, plain and persistent schedules), and the group variant spreads a
+// system over eight lanes (the group schedule, the default).
 #include "rk_launch.hpp"
+#include "rk_group.hpp"
 
 namespace rkmi {
 
@@ -56,10 +59,65 @@ struct PleiadesProblem {
   }
 };
 
+// Group variant: lane r < 7 of a group of eight holds body r's unknowns
+// (x_r, y_r, x_r', y_r') in registers; lane 7 holds none.  An evaluation
+// writes the positions to the group's LDS area, and each body's lane forms its
+// pair terms and sums in the one-lane order (the pair value of (i, j) is the
+// same bits in the lanes of i and of j), so results equal the one-lane kernels.
+struct PleiadesGroup {
+  static constexpr int N = 28;
+  static constexpr int NR = 0;
+  static constexpr int kL = 8;
+  static constexpr int kGroupLanes = 8;
+  static constexpr bool kColumns = false;
+  static constexpr int kLaneDoubles = 0;
+  static constexpr int S = 4;
+  static constexpr bool kOwnRhs = true;
+  static constexpr int kOffPos = 0;               // x_1..x_7, y_1..y_7
+  static constexpr int kOffRed = 14;              // norm scratch, N doubles
+  static constexpr int kLdsPerSystem = kOffRed + N;
+  static constexpr int kSp[S * kL] = {0,  1,  2,  3,  4,  5,  6,  -1,     // x_r
+                                      7,  8,  9,  10, 11, 12, 13, -1,     // y_r
+                                      14, 15, 16, 17, 18, 19, 20, -1,     // x_r'
+                                      21, 22, 23, 24, 25, 26, 27, -1};    // y_r'
+  using Params = const double*;
+  struct Lane {};
+  __device__ static void init(Lane&, const Params&, const double* __restrict__, int64_t, int64_t,
+                              const Grp<PleiadesGroup>&) {}
+  __device__ static void rhs(const Lane&, const Grp<PleiadesGroup>& x, const double (&y)[S],
+                             double (&f)[S]) {
+    double* const P = x.lds + kOffPos;
+    const bool body = x.r < 7;
+    if (body) {
+      P[x.r] = y[0];
+      P[7 + x.r] = y[1];
+    }
+    group_sync();
+    double ax = 0.0, ay = 0.0;
+    if (body) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        if (j == x.r) continue;
+        const double xj = P[j], yj = P[7 + j];
+        const double d2 = (y[0] - xj) * (y[0] - xj) + (y[1] - yj) * (y[1] - yj);
+        const double rinv = 1.0 / (d2 * sqrt(d2));
+        const double mj = (double)(j + 1);
+        ax += (mj * (xj - y[0])) * rinv;
+        ay += (mj * (yj - y[1])) * rinv;
+      }
+    }
+    f[0] = body ? y[2] : 0.0;
+    f[1] = body ? y[3] : 0.0;
+    f[2] = ax;
+    f[3] = ay;
+    group_sync();
+  }
+};
+
 }  // namespace rkmi
 
 extern "C" int rkmi_pleiades_launch(const rkmi::LaunchArgs* a, void* s) {
-  return rkmi::launch<rkmi::PleiadesProblem>(a, s);
+  return rkmi::launch_with_group<rkmi::PleiadesProblem, rkmi::PleiadesGroup>(a, s);
 }
 
 extern "C" int rkmi_pleiades_host(const rkmi::LaunchArgs* a) {
@@ -67,5 +125,6 @@ extern "C" int rkmi_pleiades_host(const rkmi::LaunchArgs* a) {
 }
 
 extern "C" int64_t rkmi_pleiades_workspace(int method, int schedule, int64_t n) {
-  return rkmi::workspace<rkmi::PleiadesProblem>(method, schedule, n);
+  return rkmi::workspace_with_group<rkmi::PleiadesProblem, rkmi::PleiadesGroup>(method, schedule,
+                                                                                n);
 }

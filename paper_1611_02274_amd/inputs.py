@@ -274,7 +274,7 @@ WORKLOADS = {
                            (900.0, 2800.0)),
     # ten global steps of 0.1 over [0, 1], each a restart (Sec. 4.1); eps = 1e-10
     "pleiades_rkck": Workload("pleiades_rkck", "rkck", "pleiades", 1 << 18, 0.0, 1.0, 1e-10, 0.0,
-                              6006, launch=dict(schedule=1), global_steps=10),
+                              6006, launch=dict(schedule=3), global_steps=10),
     # the energy equation: ten global steps of 1e-6 s, each a restart (Sec. 4.2)
     "net13_thermal_rkc": Workload("net13_thermal_rkc", "rkc", "net13_thermal", 1 << 18, 0.0,
                                   1e-5, 1e-8, 1e-12, 8008, (1000.0, 2500.0),

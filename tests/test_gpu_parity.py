@@ -342,11 +342,13 @@ def _pleiades_global_steps(fn_step, y0, n_global=10, t0=0.0, t1=1.0):
 
 
 @pytest.mark.parametrize("n,schedule,cost_order", [(4133, 1, 0), (4133, 2, 0), (1000, 1, 1),
-                                                   (65, 2, 1)])
+                                                   (65, 2, 1), (4133, 3, 0), (1000, 3, 1),
+                                                   (65, 0, 0), (9, 3, 0)])
 def test_pleiades_rkck(rk, orc, n, schedule, cost_order):
-    """The Pleiades problem (28 unknowns in workspace columns) under RKCK at
-    eps = 1e-10 over the ten global steps of [0, 1]: every schedule equals the
-    oracle step by step."""
+    """The Pleiades problem under RKCK at eps = 1e-10 over the ten global
+    steps of [0, 1]: one lane per system with 28 unknowns in workspace columns
+    (plain, persistent) and eight lanes per system (group, the default), each
+    equal to the oracle step by step."""
     import torch
     say(f"case pleiades n={n} schedule={schedule} cost_order={cost_order}")
     y0, _ = I.pleiades_inputs(n, 6006)
@@ -365,6 +367,22 @@ def test_pleiades_rkck(rk, orc, n, schedule, cost_order):
     yg, sg, stg = _pleiades_global_steps(gpu_step, y0)
     yo, so, sto = _pleiades_global_steps(orc_step, y0)
     compare(yg, sg, stg, yo, so, sto, 1e-10, f"pleiades n={n}")
+
+
+@pytest.mark.parametrize("schedule", [1, 3])
+def test_pleiades_rkc(rk, orc, schedule):
+    """RKC on the Pleiades problem (one global step of 0.1): the group
+    variant's RKC driver and the one-lane kernel equal the oracle."""
+    say(f"case pleiades rkc schedule={schedule}")
+    import torch
+    y0, _ = I.pleiades_inputs(700, 6008)
+    prob, pb = rk.Problem.pleiades(), orc.pleiades()
+    yd = torch.from_numpy(y0).cuda()
+    y1, st, stats = rk.integrate_rkc(prob, yd, None, 0.0, 0.1, 1e-8, 1e-10, schedule=schedule)
+    torch.cuda.synchronize()
+    yo, so, sto = orc.rkc_batch(pb, y0, None, 0.0, 0.1, 1e-8, 1e-10)
+    compare(y1.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy(), yo, so, sto, 1e-10,
+            f"pleiades rkc schedule={schedule}")
 
 
 def test_pleiades_full_size_sampled(rk, orc):
