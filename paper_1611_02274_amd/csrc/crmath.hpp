@@ -260,6 +260,42 @@ constexpr double kCbrtQuarter = 0x1.428a2f98d728bp-1;      // RN(2^(-2/3))
 constexpr double kSqrt2 = 0x1.6a09e667f3bcdp+0;
 constexpr double kLn2d = 0x1.62e42fefa39efp-1;
 
+// ln(m 2^e) for m in [1, 2) to an absolute error of about 4e-13: e ln2 +
+// 2 atanh(s), s = (m' - 1)/(m' + 1) with m' = m or m / 2 in [sqrt(1/2),
+// sqrt(2)), the series to s^13.  Enough for the small correction factors
+// x^(1/3 - RN(1/3)) and x^(RN(0.2) - 1/5) below.
+RKMI_HD double log_rough(double m, int e) {
+  double mm = m;
+  int ee = e;
+  if (mm > kSqrt2) {
+    mm = 0.5 * mm;
+    ee += 1;
+  }
+  const double sv = (mm - 1.0) / (mm + 1.0);
+  const double s2 = sv * sv;
+  const double lnm =
+      2.0 * sv *
+      (1.0 + s2 * (0x1.5555555555555p-2 +
+                   s2 * (0.2 + s2 * (0x1.2492492492492p-3 +
+                                     s2 * (0x1.c71c71c71c71cp-4 +
+                                           s2 * (0x1.745d1745d1746p-4 + s2 * 0x1.3b13b13b13b14p-4))))));
+  return (double)ee * kLn2d + lnm;
+}
+
+// x = m 2^e with m in [1, 2), for finite x > 0 (subnormals scaled).
+RKMI_HD void split_normal(double x, double& m, int& e) {
+  uint64_t b = bits_of(x);
+  int ex = (int)(b >> 52);
+  int sc = 0;
+  if (ex == 0) {
+    b = bits_of(x * 0x1p54);
+    ex = (int)(b >> 52);
+    sc = -54;
+  }
+  e = ex - 1023 + sc;
+  m = from_bits((b & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL);
+}
+
 template <bool kSquare>
 RKMI_HD void pow_third(double x, double& p1, double& p2) {
   if (x == 0.0 || x == 1.0) {
@@ -271,16 +307,9 @@ RKMI_HD void pow_third(double x, double& p1, double& p2) {
     p2 = kSquare ? cr_pow(x, 2.0 * kThird) : 0.0;
     return;
   }
-  uint64_t b = bits_of(x);
-  int ex = (int)(b >> 52);
-  int sc = 0;
-  if (ex == 0) {                  // subnormal: scale into the normal range
-    b = bits_of(x * 0x1p54);
-    ex = (int)(b >> 52);
-    sc = -54;
-  }
-  const int e = ex - 1023 + sc;   // x = m 2^e, m in [1, 2)
-  const double m = from_bits((b & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL);
+  double m;
+  int e;
+  split_normal(x, m, e);          // x = m 2^e, m in [1, 2)
   int q = e / 3, r = e - 3 * q;
   if (r < 0) {
     r += 3;
@@ -297,21 +326,7 @@ RKMI_HD void pow_third(double x, double& p1, double& p2) {
   const dd c3 = two_prod(c, c2.hi);
   const double res = (c3.hi - t) + (c3.lo + c * c2.lo);
   const double delta = res * (z * z) * kThird;   // (c^3 - t) / (3 c^2)
-  double mm = m;
-  int ee = e;
-  if (mm > kSqrt2) {
-    mm = 0.5 * mm;
-    ee += 1;
-  }
-  const double sv = (mm - 1.0) / (mm + 1.0);
-  const double s2 = sv * sv;
-  const double lnm =
-      2.0 * sv *
-      (1.0 + s2 * (0x1.5555555555555p-2 +
-                   s2 * (0.2 + s2 * (0x1.2492492492492p-3 +
-                                     s2 * (0x1.c71c71c71c71cp-4 +
-                                           s2 * (0x1.745d1745d1746p-4 + s2 * 0x1.3b13b13b13b14p-4))))));
-  const double u = -kThirdDefect * ((double)ee * kLn2d + lnm);
+  const double u = -kThirdDefect * log_rough(m, e);
   const dd P = fast_two_sum(c, c * (u + 0.5 * u * u) - delta);
   p1 = scale2(P.hi + P.lo, q);
   if (kSquare) {
@@ -330,6 +345,90 @@ RKMI_HD double pow_third_one(double x) {
   double p1, p2;
   pow_third<false>(x, p1, p2);
   return p1;
+}
+
+// (1 + d)^-y for |d| < 2^-40 and 0 < y < 1: 1 - y d + (y (y + 1) / 2) d^2
+// (the next term is below 2^-120) in double-double, rounded once.  Near 1 the
+// exact powers can lie within about 2^-104 of a rounding midpoint (x = 1 +
+// k 2^-52 gives 1 - k 2^-54 + O(k^2 2^-104) for y = 1/4), closer than the
+// root-and-Newton evaluations below resolve.
+RKMI_HD double pow_near_one(double d, double y) {
+  const dd p = two_prod(y, d);
+  const dd r = fast_two_sum(1.0, -p.hi);
+  const double c2 = 0.5 * (y * (y + 1.0));
+  return r.hi + ((r.lo - p.lo) + c2 * (d * d));
+}
+
+// x^-0.25 for finite x > 0, correctly rounded (as cr_pow(x, -0.25)): x =
+// t 2^(4q) with t in [1, 16); a0 = 1 / sqrt(sqrt(t)) (relative error below
+// 2^-50), then one Newton step for t a^4 = 1 in double-double, a = a0 - a0
+// (t a0^4 - 1) / 4 with the residual formed exactly by TwoProd: relative
+// error below about 2^-98 before the final rounding.
+RKMI_HD double pow_minus_quarter(double x) {
+  if (!(x > 0.0) || !is_finite(x)) return cr_pow(x, -0.25);
+  double m;
+  int e;
+  split_normal(x, m, e);
+  const int q = e >> 2;                       // floor(e / 4)
+  const double t = m * (double)(1 << (e - 4 * q));
+  // near a power of 16 (t near 1 or 16) the series
+  if (t - 1.0 < 0x1p-40) return scale2(pow_near_one(t - 1.0, 0.25), -q);
+  if (16.0 - t < 0x1p-36) return scale2(pow_near_one(0.0625 * t - 1.0, 0.25), -q - 1);
+  const double a0 = 1.0 / sqrt(sqrt(t));
+  const dd a2 = two_prod(a0, a0);
+  const dd a4 = two_prod(a2.hi, a2.hi);
+  const double a4lo = a4.lo + 2.0 * a2.hi * a2.lo;
+  const dd p = two_prod(t, a4.hi);
+  const double res = (p.hi - 1.0) + (p.lo + t * a4lo);
+  const dd A = fast_two_sum(a0, -0.25 * (a0 * res));
+  return scale2(A.hi + A.lo, -q);
+}
+
+// x^-RN(0.2) for finite x > 0, correctly rounded (as cr_pow(x, -0.2)).  Since
+// RN(0.2) = 1/5 + 2^-54/5 exactly, x^-RN(0.2) = x^(-1/5) (1 - u + u^2/2 ...)
+// with u = (2^-54/5) ln x, |u| < 8.3e-15.  x = t 2^(5q) with t in [1, 32):
+// t^(-1/5) from a degree-4 fit of m^(-1/5) on [1, 2) (relative error 4.2e-5;
+// the fit is ours) times 2^(-r/5), two Newton steps z <- z + z (1 - t z^5)/5
+// and one in double-double; relative error below about 2^-95.
+constexpr double kFifthDefect = 0x1.999999999999ap-57;       // RN(0.2) - 1/5, rounded
+constexpr double kFifthFit[5] = {0x1.d81ea442f789fp-1, -0x1.f71b3cd67e5e7p-4,
+                                 0x1.9206823b82378p-5, -0x1.ad6fd51751e20p-6,
+                                 0x1.d2a8f56f71fa3p-7};       // m^(-1/5) in powers of m - 3/2
+constexpr double kFifthRoot2[5] = {0x1.0000000000000p+0, 0x1.bdb8cdadbe120p-1,
+                                   0x1.8406003b2ae5cp-1, 0x1.51cb453b9536cp-1,
+                                   0x1.2611186bae674p-1};     // RN(2^(-r/5))
+
+RKMI_HD double pow_minus_fifth(double x) {
+  if (!(x > 0.0) || !is_finite(x)) return cr_pow(x, -0.2);
+  // near 1 the series (near other powers of 32 the factor x^-(RN(0.2) - 1/5)
+  // moves the value off the midpoints)
+  if (fabs(x - 1.0) < 0x1p-40) return pow_near_one(x - 1.0, 0.2);
+  double m;
+  int e;
+  split_normal(x, m, e);
+  int q = e / 5, r = e - 5 * q;
+  if (r < 0) {
+    r += 5;
+    q -= 1;
+  }
+  const double t = m * (double)(1 << r);
+  const double d = m - 1.5;
+  double z = kFifthFit[0] + d * (kFifthFit[1] + d * (kFifthFit[2] + d * (kFifthFit[3] + d * kFifthFit[4])));
+  z = z * kFifthRoot2[r];
+  for (int it = 0; it < 2; ++it) {
+    const double z2 = z * z;
+    z = z + z * (1.0 - t * (z2 * z2 * z)) * 0.2;
+  }
+  const dd z2 = two_prod(z, z);
+  const dd z4 = two_prod(z2.hi, z2.hi);
+  const double z4lo = z4.lo + 2.0 * z2.hi * z2.lo;
+  const dd z5 = two_prod(z4.hi, z);
+  const double z5lo = z5.lo + z4lo * z;
+  const dd p = two_prod(t, z5.hi);
+  const double res = (p.hi - 1.0) + (p.lo + t * z5lo);
+  const double u = kFifthDefect * log_rough(m, e);
+  const dd P = fast_two_sum(z, z * (0.5 * u * u - u) - 0.2 * (z * res));
+  return scale2(P.hi + P.lo, -q);
 }
 
 }  // namespace crm

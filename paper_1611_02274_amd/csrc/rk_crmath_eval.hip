@@ -1,8 +1,9 @@
 // rk_crmath_eval.hip -- evaluates the kernels' correctly rounded exp / log / pow
 // over arrays, on the host (the same source compiled for the CPU) or on the
 // device, so that tests can check them.  fn: 0 exp(x), 1 log(x), 2 pow(x, y),
-// 3 and 4: x^RN(1/3) and x^RN(2/3) from the controllers' pair, 5: x^RN(1/3)
-// alone (y unused for 3 to 5).
+// 3 and 4: x^RN(1/3) and x^RN(2/3) from the RKC controllers' pair, 5: x^RN(1/3)
+// alone, 6: x^-0.25, 7: x^-RN(0.2) as the RKCK controllers form them (y unused
+// for 3 to 7).
 // Not part of the public ABI.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,6 +23,8 @@ __host__ __device__ inline double eval_one(int fn, double x, double y) {
       return fn == 3 ? p1 : p2;
     }
     case 5: return rkmi::crm::pow_third_one(x);
+    case 6: return rkmi::crm::pow_minus_quarter(x);
+    case 7: return rkmi::crm::pow_minus_fifth(x);
     default: return rkmi::crm::cr_pow(x, y);
   }
 }
@@ -35,7 +38,7 @@ __global__ void crmath_kernel(int fn, int64_t n, const double* __restrict__ x,
 }  // namespace
 
 extern "C" int rkmi_crmath_host(int fn, int64_t n, const double* x, const double* y, double* out) {
-  if (fn < 0 || fn > 5 || n < 0 || (n && (!x || !y || !out))) return -1;
+  if (fn < 0 || fn > 7 || n < 0 || (n && (!x || !y || !out))) return -1;
   for (int64_t i = 0; i < n; ++i) out[i] = eval_one(fn, x[i], y[i]);
   return 0;
 }
@@ -43,7 +46,7 @@ extern "C" int rkmi_crmath_host(int fn, int64_t n, const double* x, const double
 // x, y, out: device arrays of n doubles.
 extern "C" int rkmi_crmath_device(int fn, int64_t n, const double* x, const double* y,
                                   double* out, void* stream) {
-  if (fn < 0 || fn > 5 || n < 0 || (n && (!x || !y || !out))) return -1;
+  if (fn < 0 || fn > 7 || n < 0 || (n && (!x || !y || !out))) return -1;
   if (n == 0) return 0;
   const int64_t blocks = (n + 255) / 256;
   if (blocks > 0x7fffffffLL) return -1;

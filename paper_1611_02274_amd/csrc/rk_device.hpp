@@ -50,8 +50,8 @@ namespace rkmi {
 
 constexpr double kUround = 2.22e-16;
 constexpr double kSafety = 0.9;
-constexpr double kPGrow = -0.2;
-constexpr double kPShrink = -0.25;
+constexpr double kPGrow = -0.2;      // err^kPGrow: crm::pow_minus_fifth
+constexpr double kPShrink = -0.25;   // err^kPShrink: crm::pow_minus_quarter
 constexpr double kErrCon = 1.89e-4;
 constexpr double kP1 = 0.1;
 constexpr double kRkckHmin = 1.0e-20;
@@ -374,7 +374,7 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
     if (crm::is_nan(err) || nan_flag)
       S.h = S.h * kP1;
     else
-      S.h = fmax(kSafety * S.h * crm::cr_pow(err, kPShrink), kP1 * S.h);
+      S.h = fmax(kSafety * S.h * crm::pow_minus_quarter(err), kP1 * S.h);
     if (!(S.h >= kRkckHmin)) {
       S.status = kSysHmin;
       return false;
@@ -383,7 +383,7 @@ RKMI_HD bool rkck_attempt(const typename Prob::Lane& L, const typename Prob::Par
     S.cut = S.h < S.h_want;
     S.t += S.h;
     const double hacc = S.h;
-    const double hn = (err > kErrCon) ? kSafety * S.h * crm::cr_pow(err, kPGrow) : S.h * 5.0;
+    const double hn = (err > kErrCon) ? kSafety * S.h * crm::pow_minus_fifth(err) : S.h * 5.0;
     S.h = fmax(kRkckHmin, fmin(c.hmax, hn));
     copy<Prob>(S.y, yt);
     ++S.n_acc;

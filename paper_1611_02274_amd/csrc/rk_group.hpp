@@ -280,7 +280,7 @@ struct GRkck {
       if (crm::is_nan(err) || nan_flag)
         h = h * kP1;
       else
-        h = fmax(kSafety * h * crm::cr_pow(err, kPShrink), kP1 * h);
+        h = fmax(kSafety * h * crm::pow_minus_quarter(err), kP1 * h);
       if (!(h >= kRkckHmin)) {
         status = kSysHmin;
         return false;
@@ -288,7 +288,7 @@ struct GRkck {
     } else {
       cut = h < h_want;
       t += h;
-      const double hn = (err > kErrCon) ? kSafety * h * crm::cr_pow(err, kPGrow) : h * 5.0;
+      const double hn = (err > kErrCon) ? kSafety * h * crm::pow_minus_fifth(err) : h * 5.0;
       h = fmax(kRkckHmin, fmin(c.hmax, hn));
       gcopy<GP>(y, yt);
       ++n_acc;

@@ -122,6 +122,30 @@ def test_kernel_pow_third_is_correctly_rounded(orc):
     assert np.array_equal(run(4, xb, yb), np.array([orc.cr_pow(v, 2.0 / 3.0) for v in xb]))
 
 
+def test_kernel_rkck_powers_are_correctly_rounded(orc):
+    """The RKCK controllers' err^-0.25 (fourth root refined in double-double)
+    and err^-RN(0.2) (fifth root times x^-(RN(0.2) - 1/5)) are the correctly
+    rounded powers over the whole positive range."""
+    run = _kernel_math()
+    rng = np.random.default_rng(9)
+    x = np.concatenate([10 ** rng.uniform(-300, 300, 4000), rng.uniform(1e-4, 1, 3000),
+                        rng.uniform(1, 100, 2000), 1.0 + 10 ** rng.uniform(-16, -2, 300),
+                        1.0 - 10 ** rng.uniform(-16, -2, 300), 2.0 ** rng.integers(-1074, 1023, 300),
+                        # within a few ulps of 1 the values lie near rounding midpoints
+                        1.0 + np.arange(1, 64) * 2.0 ** -52, 1.0 - np.arange(1, 64) * 2.0 ** -53,
+                        1.0 + np.arange(1, 64) * 2.0 ** -40,
+                        np.outer(16.0 ** np.arange(-20, 20), 1.0 + np.arange(-8, 9) * 2.0 ** -52).ravel(),
+                        np.outer(32.0 ** np.arange(-20, 20), 1.0 + np.arange(-8, 9) * 2.0 ** -52).ravel(),
+                        [1.0, 5e-324, 2.0 ** -1022, 16.0, 32.0, 0.0625, 1.7976931348623157e308]])
+    y = np.zeros(x.size)
+    for fn, p in ((6, -0.25), (7, -0.2)):
+        got = run(fn, x, y)
+        assert got.tolist() == [_cr(mp.power(mp.mpf(float(v)), mp.mpf(p))) for v in x], fn
+        xb = np.concatenate([rng.uniform(1e-4, 1, 100_000), 10 ** rng.uniform(0, 10, 50_000)])
+        assert np.array_equal(run(fn, xb, np.zeros(xb.size)),
+                              np.array([orc.cr_pow(v, p) for v in xb])), fn
+
+
 def test_kernel_math_special_values():
     run = _kernel_math()
     inf, nan = float("inf"), float("nan")

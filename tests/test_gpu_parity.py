@@ -194,9 +194,12 @@ def test_device_math_equals_host_and_oracle(rk, orc):
              (2, 10 ** rng.uniform(-20, 3, n), np.full(n, 2.0 / 3.0)),
              (3, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
              (4, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
-             (5, 10 ** rng.uniform(-30, 6, n), np.zeros(n))]
+             (5, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
+             (6, 10 ** rng.uniform(-30, 6, n), np.zeros(n)),
+             (7, 10 ** rng.uniform(-30, 6, n), np.zeros(n))]
     ref = {0: orc.cr_exp, 1: orc.cr_log, 3: lambda v, w: orc.cr_pow(v, 1.0 / 3.0),
-           4: lambda v, w: orc.cr_pow(v, 2.0 / 3.0), 5: lambda v, w: orc.cr_pow(v, 1.0 / 3.0)}
+           4: lambda v, w: orc.cr_pow(v, 2.0 / 3.0), 5: lambda v, w: orc.cr_pow(v, 1.0 / 3.0),
+           6: lambda v, w: orc.cr_pow(v, -0.25), 7: lambda v, w: orc.cr_pow(v, -0.2)}
     for fn, x, y in cases:
         xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
         od = torch.empty_like(xd)
