@@ -459,8 +459,10 @@ def main():
             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
             "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
             "kernel_ms": kern_ms, "algorithmic_flops_per_launch": flops,
-            "kernel_ms_covers": ("pilot, sort and integration kernels of one call"
-                                 if launch.get("cost_order") else "the integration kernel"),
+            "kernel_ms_covers": (("pilot, sort and integration kernels" if launch.get("cost_order")
+                                  else "the integration kernel") +
+                                 (f" of each of the {n_global} global-step calls" if n_global > 1
+                                  else " of one call")),
         },
     }
     if not args.no_cpu_baseline:
