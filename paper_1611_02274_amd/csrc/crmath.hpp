@@ -188,7 +188,37 @@ RKMI_HD dd log_dd(double x) {
   return two_sum(t3.hi, lo);
 }
 
-RKMI_HD double cr_exp(double x) { return exp_dd(x, 0.0); }
+// exp(x) correctly rounded.  A first evaluation: the reduction of exp_dd
+// (r + rl = x - k ln2/1024 to 2^-115), 1 + r + (rl (1 + r) + r^2 (1/2 + r/6 +
+// r^2/24 + r^3/120)) as a double-double (relative error below 2^-74.5: the
+// truncation r^6/720 < 2^-78.5 and the rounding of the r^2 terms), times the
+// double-double 2^(j/1024): relative error below 2^-74 in all.  When the
+// double-double result R lies farther than 2^-70 from the midpoints around
+// R.hi, the exact value rounds to R.hi; that fails for about 2^-17 of inputs
+// (and where R.hi is a power of two), which take exp_dd, as do the ends of the
+// range (subnormal results, overflow, NaN).
+RKMI_HD double cr_exp(double x) {
+  if (!(x > -708.3 && x < 709.7)) return exp_dd(x, 0.0);
+  const double kd = rint(x * kInvL);
+  const double rh = x - kd * kL1;                  // exact
+  const dd p = two_prod(kd, kL2);
+  const dd s = two_sum(rh, -p.hi);
+  const double rl = (s.lo - p.lo) - kd * kL3;
+  const double r = s.hi;
+  const double q = (r * r) * (0.5 + r * (0x1.5555555555555p-3 +
+                                         r * (0x1.5555555555555p-5 + r * 0x1.1111111111111p-7)));
+  const dd e1 = fast_two_sum(1.0, r);
+  const dd E = fast_two_sum(e1.hi, e1.lo + ((rl + rl * r) + q));
+  const int64_t k = (int64_t)kd;
+  const int64_t m = k >> 10;
+  const int jj = (int)(k - (m << 10));
+  const int j1 = jj >> 5, j2 = jj & 31;
+  const dd T = dd_mul(dd{kExpT1[2 * j1], kExpT1[2 * j1 + 1]}, dd{kExpT2[2 * j2], kExpT2[2 * j2 + 1]});
+  const dd R = dd_mul(T, E);
+  const double half_ulp = R.hi >= 2.0 ? 0x1p-52 : (R.hi >= 1.0 ? 0x1p-53 : 0x1p-54);
+  if (fabs(R.lo) < half_ulp - 0x1p-70 && R.hi != 1.0 && R.hi != 2.0) return scale2(R.hi, (int)m);
+  return exp_dd(x, 0.0);
+}
 
 RKMI_HD double cr_log(double x) {
   if (x != x) return x;
