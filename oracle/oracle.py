@@ -28,7 +28,7 @@ _ip = C.POINTER(C.c_int32)
 class _Problem(C.Structure):
     _fields_ = [("kind", C.c_int), ("n_eq", C.c_int), ("n_param", C.c_int), ("A", _dp),
                 ("n_rx", C.c_int), ("reac", _ip), ("prod", _ip), ("lnA", _dp), ("beta", _dp),
-                ("Ea", _dp), ("Keq", _dp), ("W", _dp), ("thermo", _dp)]
+                ("Ea", _dp), ("Keq", _dp), ("W", _dp), ("thermo", _dp), ("sr_method", C.c_int)]
 
 
 def _d(a):
@@ -60,6 +60,7 @@ def lib():
             "orc_rkc_step": (C.c_int, [P, _dp, C.c_double, _dp, _dp, C.c_double, C.c_int, _dp]),
             "orc_rkc_stages": (C.c_int, [P, _dp, C.c_double, _dp, _dp, C.c_double, C.c_int,
                                          _dp]),
+            "orc_gershgorin": (C.c_double, [P, _dp, _dp, _dp]),
             "orc_spec_rad": (C.c_double, [P, _dp, C.c_double, _dp, _dp, C.c_double, _dp, C.c_int,
                                           C.POINTER(C.c_int)]),
             "orc_rkc_mmax": (C.c_int, [C.c_double]),
@@ -112,10 +113,12 @@ def lib():
 class Problem:
     """A problem description for the oracle; keeps its arrays alive."""
 
-    def __init__(self, kind, n_eq, n_param, A=None, net=None, lnA=None):
+    def __init__(self, kind, n_eq, n_param, A=None, net=None, lnA=None, sr_method=0):
         self._keep = []
         s = _Problem()
         s.kind, s.n_eq, s.n_param = kind, n_eq, n_param
+        s.sr_method = sr_method
+        self.sr_method = sr_method
         if A is not None:
             A = np.ascontiguousarray(A, dtype=np.float64)
             self._keep.append(A)
@@ -152,11 +155,28 @@ class Problem:
         return lib().orc_n_theta(self.ptr)
 
     def with_lnA(self, lnA):
-        return Problem(MASS_ACTION, self.n_eq, self.n_param, net=self.net, lnA=lnA)
+        return Problem(MASS_ACTION, self.n_eq, self.n_param, net=self.net, lnA=lnA,
+                       sr_method=self.sr_method)
+
+    def gershgorin(self, g, y):
+        """(sigma, J): the Gershgorin bound and the analytic Jacobian df/dy at
+        y (one system, g its parameters)."""
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        J = np.zeros((self.n_eq, self.n_eq))
+        sig = lib().orc_gershgorin(self.ptr, _d(g), _d(y), _d(J))
+        if sig < 0.0:
+            raise ValueError("no analytic Jacobian for this problem")
+        return sig, J
 
 
-def vdp():
-    return Problem(VDP, 2, 1)
+# RKC spectral radius: the nonlinear power method (Appendix) or the Gershgorin
+# bound of the analytic Jacobian
+SR_POWER, SR_GERSHGORIN = 0, 1
+
+
+def vdp(sr_method=SR_POWER):
+    return Problem(VDP, 2, 1, sr_method=sr_method)
 
 
 def linear(A):
@@ -164,8 +184,8 @@ def linear(A):
     return Problem(LINEAR, A.shape[0], 0, A=A)
 
 
-def network(net):
-    return Problem(MASS_ACTION, net.n_sp, 2, net=net)
+def network(net, sr_method=SR_POWER):
+    return Problem(MASS_ACTION, net.n_sp, 2, net=net, sr_method=sr_method)
 
 
 def network_thermal(net):

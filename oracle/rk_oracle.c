@@ -85,6 +85,9 @@ static int check_problem(const orc_problem *pb) {
   if (pb->kind != ORC_VDP && pb->kind != ORC_LINEAR && pb->kind != ORC_MASS_ACTION &&
       pb->kind != ORC_PLEIADES && pb->kind != ORC_MASS_ACTION_THERMAL)
     return -1;
+  if (pb->sr_method != 0 &&
+      (pb->sr_method != 1 || (pb->kind != ORC_VDP && pb->kind != ORC_MASS_ACTION) || pb->n_eq > 16))
+    return -1;
   return 0;
 }
 
@@ -231,6 +234,78 @@ static void rhs(const orc_sys *S, double t, const double *y, double *f) {
     }
     for (int k = 0; k < N; ++k) f[k] = (pb->W[k] * omega[k]) * S->irho;
   }
+}
+
+/* Analytic Jacobian J = df/dy of Eq. (1) at y and its Gershgorin bound.  The
+ * Appendix names the circle theorem as an alternative to the power method: every
+ * eigenvalue lies in a disc |z - J_kk| <= sum_{i != k} |J_ki|, so the spectral
+ * radius is at most max_k sum_i |J_ki|.  Readings: rows k in order, each row sum
+ * over i in order from zero, the maximum by fmax from zero; the bound is used as
+ * sigma as it is (it needs no safety factor).
+ *   van der Pol: J = [[0, 1], [-2 mu y_0 y_1 - 1, mu (1 - y_0^2)]], left to right.
+ *   mass action (isothermal): with C_i = rho Y_i / W_i, [M] = sum_i C_i and
+ *   q_j = (k_f C_r0) X_r1 - (k_r C_p0) X_p1 (X = C, or [M] for an empty slot),
+ *   J_ki = (W_k D_ki) / W_i (the rho factors cancel; the division as the
+ *   reciprocal), D_ki = sum_j nu_kj g_ji over the reactions in order with
+ *   nu_kj = (products - reactants) count of k nonzero, and
+ *   g_ji = dq_j/dC_i through C_i and [M]: k_f t_f - k_r t_r with
+ *   t_f = [r0 = i] X_r1 + [r1 = i or empty] C_r0 (terms absent where zero),
+ *   t_r likewise. */
+static void jacobian(const orc_sys *S, const double *y, double *J) {
+  const orc_problem *pb = S->pb;
+  const int N = pb->n_eq;
+  if (pb->kind == ORC_VDP) {
+    const double mu = S->g[0];
+    J[0] = 0.0;
+    J[1] = 1.0;
+    J[2] = -2.0 * mu * y[0] * y[1] - 1.0;
+    J[3] = mu * (1.0 - y[0] * y[0]);
+    return;
+  }
+  double C[ORC_MAXN];
+  double M = 0.0;
+  for (int k = 0; k < N; ++k) C[k] = (S->rho * y[k]) * S->invW[k];
+  for (int k = 0; k < N; ++k) M += C[k];
+  for (int k = 0; k < N; ++k)
+    for (int i = 0; i < N; ++i) {
+      double D = 0.0;
+      for (int j = 0; j < pb->n_rx; ++j) {
+        const int r0 = pb->reac[2 * j], r1 = pb->reac[2 * j + 1];
+        const int p0 = pb->prod[2 * j], p1 = pb->prod[2 * j + 1];
+        const int nu = (p0 == k) + (p1 == k) - (r0 == k) - (r1 == k);
+        if (nu == 0) continue;
+        const double xr1 = r1 >= 0 ? C[r1] : M, xp1 = p1 >= 0 ? C[p1] : M;
+        const double tf = (r0 == i ? xr1 : 0.0) + ((r1 < 0 || r1 == i) ? C[r0] : 0.0);
+        const double tr = (p0 == i ? xp1 : 0.0) + ((p1 < 0 || p1 == i) ? C[p0] : 0.0);
+        D += (double)nu * (S->kf[j] * tf - S->kr[j] * tr);
+      }
+      J[k * N + i] = (pb->W[k] * D) * S->invW[i];
+    }
+}
+
+static double gershgorin(const orc_sys *S, const double *y, double *Jout) {
+  const int N = S->pb->n_eq;
+  double Jl[ORC_MAXN * 16];
+  double *J = Jout ? Jout : Jl;
+  jacobian(S, y, J);
+  double sigma = 0.0;
+  for (int k = 0; k < N; ++k) {
+    double r = 0.0;
+    for (int i = 0; i < N; ++i) r += fabs(J[k * N + i]);
+    sigma = fmax(sigma, r);
+  }
+  return sigma;
+}
+
+double orc_gershgorin(const orc_problem *pb, const double *g, const double *y, double *jac) {
+  if (check_problem(pb) || (pb->kind != ORC_VDP && pb->kind != ORC_MASS_ACTION) || pb->n_eq > 16)
+    return -1.0;
+  orc_sys *S = (orc_sys *)malloc(sizeof(orc_sys));
+  if (!S) return -1.0;
+  sys_init(S, pb, g);
+  const double s = gershgorin(S, y, jac);
+  free(S);
+  return s;
 }
 
 int orc_n_theta(const orc_problem *pb) {
@@ -908,11 +983,16 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
     if (1.1 * h >= fabs(t1 - t)) h = fabs(t1 - t);
     /* spectral radius at the first step and every 25 accepted steps */
     if (nstep % 25 == 0) {
-      int it = 0;
-      sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
-      n_sr++;
-      n_pow += it;
-      n_rhs += it;
+      if (pb->sr_method == 1) {
+        sigma = gershgorin(S, y_n, NULL);
+        n_sr++;
+      } else {
+        int it = 0;
+        sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
+        n_sr++;
+        n_pow += it;
+        n_rhs += it;
+      }
     }
     if (first) {
       /* initial step: trial Euler step of size 1/sigma (Sec. 2.2) */
@@ -957,11 +1037,16 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
         h = 0.8 * h / orc_cr_pow(err, 1.0 / 3.0);
       else
         h = P1 * h;
-      int it = 0;
-      sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
-      n_sr++;
-      n_pow += it;
-      n_rhs += it;
+      if (pb->sr_method == 1) {
+        sigma = gershgorin(S, y_n, NULL);
+        n_sr++;
+      } else {
+        int it = 0;
+        sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
+        n_sr++;
+        n_pow += it;
+        n_rhs += it;
+      }
       if (!(h >= hmin)) {
         status = ORC_HMIN;
         break;

@@ -72,11 +72,19 @@ typedef struct {
   const double *W;     /* [n_sp] molar masses */
   const double *thermo;/* ORC_MASS_ACTION_THERMAL: [3][n_sp] (u0, c, d): e_k(T) = u0 + (c + d T) T,
                           c_v,k(T) = c + 2 d T, per unit mass */
+  int sr_method;       /* RKC spectral radius: 0 the nonlinear power method (Appendix),
+                          1 the Gershgorin bound of the analytic Jacobian (ORC_VDP and
+                          ORC_MASS_ACTION only) */
 } orc_problem;
 
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Gershgorin bound max_k sum_i |J_ki| of J = df/dy at y for system g (ORC_VDP,
+ * ORC_MASS_ACTION); J itself row-major into jac [N][N] when jac is not NULL.
+ * Returns -1.0 for other problem kinds. */
+double orc_gershgorin(const orc_problem *pb, const double *g, const double *y, double *jac);
 
 /* ---- building blocks (exported so the tests can pin each one) ---- */
 /* exp, log and pow correctly rounded (evaluated in binary128, rounded once) */
