@@ -45,7 +45,7 @@ def measured_traffic(workload: str):
     return None, None
 
 
-def cpu_baseline(w, net, y0, g, target_s: float):
+def cpu_baseline(w, net, y0, g, target_s: float, sr_method: int = 0):
     """The oracle (serial per system, OpenMP across systems) on a bounded sample."""
     import numpy as np
 
@@ -53,7 +53,9 @@ def cpu_baseline(w, net, y0, g, target_s: float):
     pleiades = isinstance(net, str)
     thermal = w.problem.endswith("_thermal")
     pb = (orc.vdp() if net is None else orc.pleiades() if pleiades
-          else orc.network_thermal(net) if thermal else orc.network(net))
+          else orc.network_thermal(net) if thermal else orc.network(net, sr_method))
+    if net is None:
+        pb = orc.vdp(sr_method)
     fn = orc.rkck_batch if w.method == "rkck" else orc.rkc_batch
     cores = orc.max_threads()
     n_global = w.global_steps
@@ -325,6 +327,9 @@ def main():
                          "-1: the workload's own choice")
     ap.add_argument("--refill", type=int, default=0,
                     help="persistent schedule: idle lanes that trigger a refill (0: default)")
+    ap.add_argument("--sr-method", default="power", choices=("power", "gershgorin"),
+                    help="RKC spectral radius: the nonlinear power method or the Gershgorin "
+                         "bound of the analytic Jacobian (van der Pol, networks up to 16 species)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device-to-device copy of 1 GiB, three times (the known "
                          "traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -384,6 +389,8 @@ def main():
         launch["schedule"] = {"auto": 0, "plain": 1, "persistent": 2, "group": 3}[args.schedule]
     if args.cost_order >= 0:
         launch["cost_order"] = args.cost_order
+    if args.sr_method != "power":
+        launch["sr_method"] = args.sr_method
     if args.refill:
         launch["refill"] = args.refill
     sched_name = {0: "automatic (group for more than 16 species, else persistent)",
@@ -431,7 +438,8 @@ def main():
     flops = sum(FL.total(w.method, x, prob.n_eq, FL.Thermal(net) if thermal else net)
                 for x in st_all)
     achieved = flops / (kern_ms * 1e-3) / 1e12
-    traffic, traffic_src = measured_traffic(w.name)
+    traffic, traffic_src = measured_traffic(w.name + ("_gershgorin" if launch.get("sr_method")
+                                                      else ""))
     value = w.n * args.steps / elapsed
     res = {
         "metric": METRIC,
@@ -467,7 +475,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline(w, net, y0, g, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(w, net, y0, g, args.cpu_seconds,
+                                           1 if launch.get("sr_method") == "gershgorin" else 0)
         res["cpu_baseline"]["gpu_speedup"] = value / res["cpu_baseline"]["value"]
     print(json.dumps(res), flush=True)
 

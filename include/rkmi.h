@@ -102,7 +102,13 @@ typedef struct {
                            estimated by a pilot integration at loosened tolerances (see
                            RK_SCHED_* below); results are unchanged.  Not for taped
                            integrations or batches (RK_EUNSUPPORTED). */
-  int32_t reserved[5];  /* set to 0 */
+  int32_t sr_method;    /* RKC spectral radius: 0 the nonlinear power method (Appendix),
+                           1 the Gershgorin bound max_k sum_i |J_ki| of the analytic
+                           Jacobian (the Appendix's circle-theorem alternative; van der Pol
+                           and the isothermal networks of up to 16 species, RK_EUNSUPPORTED
+                           otherwise and for taped integrations and batches); unused by
+                           RKCK */
+  int32_t reserved[4];  /* set to 0 */
 } rk_options;
 
 /* Library version (major * 10000 + minor * 100 + patch). */

@@ -105,9 +105,15 @@ class Problem:
             _lib._lib.rk_problem_destroy(h)
 
 
+SR_METHODS = {"power": 0, "gershgorin": 1}
+
+
 def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refill=None,
-             cost_order=None):
-    if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill, cost_order)):
+             cost_order=None, sr_method=None):
+    """rk_options; sr_method (RKC spectral radius): "power" (the nonlinear power
+    method, default) or "gershgorin" (the bound of the analytic Jacobian)."""
+    if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill, cost_order,
+                               sr_method)):
         return None
     o = _lib.Options()
     o.max_steps = int(max_steps or 0)
@@ -116,6 +122,7 @@ def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refil
     o.schedule = int(schedule or 0)
     o.refill = int(refill or 0)
     o.cost_order = int(bool(cost_order))
+    o.sr_method = SR_METHODS[sr_method] if isinstance(sr_method, str) else int(sr_method or 0)
     return o
 
 

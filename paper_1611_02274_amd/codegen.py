@@ -43,6 +43,66 @@ def group_lanes(n_sp: int) -> int:
     return 16 if n_sp <= 32 else 32
 
 
+def _gershgorin_source(net) -> str:
+    """Gershgorin bound max_k sum_i |J_ki| of the analytic Jacobian at y, in
+    the reference evaluation's order: C and [M] as in the right-hand side;
+    J_ki = (W_k D_ki) (1/W_i), D_ki the sum over the reactions in order with
+    nu_kj != 0 of nu_kj g_ji, g_ji = k_f t_f - k_r t_r, t_f = [r0 = i] X_r1 +
+    [r1 = i or empty] C_r0 (t_r likewise); rows summed over i from zero, the
+    maximum by fmax from zero.  Entries and terms that are zero by structure
+    are left out (adding a zero changes no sum here)."""
+    n, nr = net.n_sp, net.n_rx
+    lines = ["  static constexpr bool kGershgorin = true;",
+             "  template <class VI>",
+             "  RKMI_HD static double gershgorin(const Lane& L, const Params& p, const VI& y) {",
+             "    const double* __restrict__ iK = p + 3 * NR;",
+             "    const double* __restrict__ W = p + 4 * NR;",
+             "    const double* __restrict__ iW = W + N;",
+             "    const int z = opaque_zero();",
+             "    double C[N];",
+             "#pragma unroll",
+             "    for (int k = 0; k < N; ++k) C[k] = (L.rho * y[k]) * ld_uniform(iW, k);",
+             "    double M = 0.0;",
+             "#pragma unroll",
+             "    for (int k = 0; k < N; ++k) M += C[k];",
+             "    double sigma = 0.0;"]
+
+    def x(s):
+        return f"C[{s}]" if s >= 0 else "M"
+    for k in range(n):
+        rx = []
+        for j in range(nr):
+            r0, r1 = int(net.reac[j][0]), int(net.reac[j][1])
+            p0, p1 = int(net.prod[j][0]), int(net.prod[j][1])
+            nu = (p0 == k) + (p1 == k) - (r0 == k) - (r1 == k)
+            if nu:
+                rx.append((j, nu, r0, r1, p0, p1))
+        lines.append("    {")
+        for j, *_ in rx:
+            lines.append(f"      const double kf{j} = L.kf[z + {j} * kLdsStride];")
+            lines.append(f"      const double kr{j} = kf{j} * ld_uniform(iK, {j});")
+        lines.append("      double r = 0.0;")
+        for i in range(n):
+            terms = []
+            for j, nu, r0, r1, p0, p1 in rx:
+                tf = ([x(r1)] if r0 == i else []) + ([x(r0)] if (r1 < 0 or r1 == i) else [])
+                tr = ([x(p1)] if p0 == i else []) + ([x(p0)] if (p1 < 0 or p1 == i) else [])
+                if not tf and not tr:
+                    continue
+                fs = f"kf{j} * ({' + '.join(tf)})" if tf else None
+                rs = f"kr{j} * ({' + '.join(tr)})" if tr else None
+                g = f"{fs} - {rs}" if fs and rs else (fs if fs else f"-({rs})")
+                terms.append({1: f"({g})", -1: f"-({g})", 2: f"2.0 * ({g})",
+                              -2: f"-2.0 * ({g})"}[nu])
+            if terms:
+                lines.append(f"      r += fabs((ld_uniform(W, {k}) * ({' + '.join(terms)})) * "
+                             f"ld_uniform(iW, {i}));")
+        lines.append("      sigma = fmax(sigma, r);")
+        lines.append("    }")
+    lines += ["    return sigma;", "  }"]
+    return "\n".join(lines) + "\n"
+
+
 def rhs_source(net, tag: str) -> tuple[str, str]:
     """Every operation is written in the order of the reference evaluation
     (products left to right, rate of progress as forward minus reverse, species
@@ -63,7 +123,7 @@ def rhs_source(net, tag: str) -> tuple[str, str]:
             if k >= 0:
                 lines.append(f"    om[{int(k)}] += q;")
     body = "\n".join(lines)
-    vjp = "" if columns else _vjp_source(net)
+    vjp = "" if columns else _vjp_source(net) + _gershgorin_source(net)
     group = group_source(net, tag) if columns else ""
     fast = (f"template <>\nstruct FastVariant<gen_{tag}::Net> {{\n  using type = gen_{tag}::GNet;\n}};\n\n"
             if columns else "")

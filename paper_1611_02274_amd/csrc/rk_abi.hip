@@ -67,6 +67,7 @@ struct rk_problem_s {
   rkmi::adjoint_fn adjoint = nullptr;
   rkmi::adjoint_host_fn adjoint_host = nullptr;
   int gen_index = -1;                  // row of the network registry
+  bool gershgorin = false;             // has the analytic Jacobian (sr_method 1)
   std::vector<double> host_prm;        // uniform problem data, device layout
   double* dev_prm[kMaxDevices] = {};   // per-device copies, made on first use
   std::mutex mu;
@@ -142,6 +143,7 @@ void fill_ctl(rkmi::Ctl& c, double t0, double t1, double rtol, double atol,
   c.mmax = mmax < 2 ? 2 : mmax;
   c.sr_period = (opt && opt->sr_period > 0) ? opt->sr_period : 25;
   c.sr_itmax = (opt && opt->sr_itmax > 0) ? opt->sr_itmax : 50;
+  c.sr_method = opt ? opt->sr_method : rkmi::kSrPower;
   c.refill = (opt && opt->refill > 0) ? (opt->refill > rkmi::kLdsStride ? rkmi::kLdsStride
                                                                         : opt->refill)
                                       : rkmi::kDefaultRefill;
@@ -186,10 +188,16 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(RK_EINVAL, "rtol must be positive");
   if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(RK_EINVAL, "atol must be >= 0");
   if (opt) {
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 4; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedGroup)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
+    if (opt->sr_method != rkmi::kSrPower && opt->sr_method != rkmi::kSrGershgorin)
+      return fail(RK_EINVAL, "sr_method must be 0 (power method) or 1 (Gershgorin)");
+    if (opt->sr_method == rkmi::kSrGershgorin && method == rkmi::kMethodRkc &&
+        (!p->gershgorin || tape))
+      return fail(RK_EUNSUPPORTED, "the Gershgorin bound needs the analytic Jacobian (van der "
+                  "Pol, isothermal networks of up to 16 species) and no tape");
     if (opt->cost_order && tape)
       return fail(RK_EUNSUPPORTED, "cost_order is not available for a taped integration");
   }
@@ -253,6 +261,7 @@ int rk_problem_create_vdp(rk_problem* out) {
   rk_problem p = new (std::nothrow) rk_problem_s();
   if (!p) return fail(RK_ENOMEM, "out of host memory");
   p->kind = kVdp;
+  p->gershgorin = true;
   p->n_eq = 2;
   p->n_param = 1;
   p->n_theta = 1;
@@ -333,6 +342,7 @@ int create_mass_action(const rk_mech_desc* d, const double* thermo, rk_problem* 
   rk_problem p = new (std::nothrow) rk_problem_s();
   if (!p) return fail(RK_ENOMEM, "out of host memory");
   p->kind = thermo ? kMassActionThermal : kMassAction;
+  p->gershgorin = !thermo && d->n_sp <= 16;
   p->n_eq = d->n_sp + (thermo ? 1 : 0);
   p->n_param = thermo ? 1 : 2;
   p->n_theta = thermo ? 0 : d->n_rx;
@@ -757,10 +767,12 @@ int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
   if (!b) return fail(RK_EINVAL, "batch handle is NULL");
   if (!n_sys || !y || !g) return fail(RK_EINVAL, "n_sys, y and g are required");
   if (opt) {
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 4; ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->cost_order)
       return fail(RK_EUNSUPPORTED, "cost_order is not available for a batch");
+    if (opt->sr_method)
+      return fail(RK_EUNSUPPORTED, "sr_method is not available for a batch");
   }
   rkmi::BatchArgs a;
   int rc = batch_args(b, n_sys, y, g, status, stats, slot_map, n_total, t0, dt, n_substeps, rtol,
@@ -795,6 +807,25 @@ int rkmi_test_host_integrate(int32_t method, rk_problem p, int64_t n, const doub
     return fail(RK_EINVAL, "invalid arguments");
   rk_options o{};
   o.max_steps = max_steps;
+  rkmi::LaunchArgs a;
+  fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0, &o);
+  a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();
+  return p->host(&a);
+}
+
+// As rkmi_test_host_integrate with the RKC spectral radius of sr_method.
+int rkmi_test_host_integrate_sr(int32_t method, rk_problem p, int64_t n, const double* y0,
+                                double* y1, const double* g, double t0, double t1, double rtol,
+                                double atol, int32_t* status, int32_t* stats, int64_t max_steps,
+                                int32_t sr_method) {
+  g_err.clear();
+  if (!p || !p->host || n < 0 || !y0 || !y1 || (p->n_param && !g) || !(t1 > t0) ||
+      !(rtol > 0.0) || !(atol >= 0.0) || sr_method < 0 || sr_method > 1 ||
+      (sr_method == 1 && !p->gershgorin))
+    return fail(RK_EINVAL, "invalid arguments");
+  rk_options o{};
+  o.max_steps = max_steps;
+  o.sr_method = sr_method;
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, nullptr, 0, &o);
   a.prm = p->host_prm.empty() ? nullptr : p->host_prm.data();

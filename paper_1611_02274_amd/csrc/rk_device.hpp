@@ -676,6 +676,50 @@ RKMI_HD void rkc_begin(const typename Prob::Lane& L, const typename Prob::Params
 
 // One attempted step of the RKC driver (Sec. 3.2); returns true while the
 // system still has to step (t < t1 and no failure).
+// A problem with an analytic Jacobian (Prob::kGershgorin, Prob::gershgorin(L,
+// prm, y) = max_k sum_i |J_ki|, rows and sums in order).
+template <class P, class = void>
+struct HasGershgorin {
+  static constexpr bool value = false;
+};
+template <class P>
+struct HasGershgorin<P, std::void_t<decltype(P::kGershgorin)>> {
+  static constexpr bool value = P::kGershgorin;
+};
+
+// The problem P with sigma from its Gershgorin bound: kernels of their own
+// (the launchers pick them for sr_method kSrGershgorin), so the bound's
+// registers do not weigh on the power-method kernels.
+template <class P>
+struct WithGershgorin : P {
+  static constexpr bool kSigmaFromGershgorin = true;
+};
+template <class P, class = void>
+struct SigmaFromGershgorin {
+  static constexpr bool value = false;
+};
+template <class P>
+struct SigmaFromGershgorin<P, std::void_t<decltype(P::kSigmaFromGershgorin)>> {
+  static constexpr bool value = P::kSigmaFromGershgorin;
+};
+
+// sigma at y_n: the Gershgorin bound in the WithGershgorin kernels, else the
+// nonlinear power method.
+template <class Prob>
+RKMI_HD void rkc_refresh_sigma(const typename Prob::Lane& L, const typename Prob::Params& prm,
+                               const Ctl& c, RkcState<Prob>& S, double* slot) {
+  if constexpr (SigmaFromGershgorin<Prob>::value) {
+    S.sigma = Prob::gershgorin(L, prm, S.yn);
+    ++S.n_sr;
+    return;
+  }
+  int it;
+  S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, c.hmax, c.sr_itmax, slot, it);
+  ++S.n_sr;
+  S.n_pow += it;
+  S.n_rhs += it;
+}
+
 template <class Prob, class Rec = NoRec>
 RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Params& prm,
                          const Ctl& c, RkcState<Prob>& S, double* slot, Rec* rec = nullptr) {
@@ -687,13 +731,8 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   }
   S.h_want = S.h;
   if (1.1 * S.h >= fabs(c.t1 - S.t)) S.h = fabs(c.t1 - S.t);
-  if (S.sr_phase == 0) {          // nstep % sr_period == 0
-    int it;
-    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
-    ++S.n_sr;
-    S.n_pow += it;
-    S.n_rhs += it;
-  }
+  if (S.sr_phase == 0)            // nstep % sr_period == 0
+    rkc_refresh_sigma<Prob>(L, prm, c, S, slot);
   Vec<Prob> y = work_vec<Prob>(slot, kCY), F1 = work_vec<Prob>(slot, kCF1);
   if (S.first) {
     // initial step from a trial Euler step of size min(hMax, 1/sigma)
@@ -735,11 +774,7 @@ RKMI_HD bool rkc_attempt(const typename Prob::Lane& L, const typename Prob::Para
   if (err > 1.0 || !crm::is_finite(err)) {
     ++S.n_rej;
     S.h = crm::is_finite(err) ? 0.8 * S.h / crm::pow_third_one(err) : kP1 * S.h;
-    int it;
-    S.sigma = spec_rad<Prob>(L, prm, S.yn, S.Fn, hmax, c.sr_itmax, slot, it);
-    ++S.n_sr;
-    S.n_pow += it;
-    S.n_rhs += it;
+    rkc_refresh_sigma<Prob>(L, prm, c, S, slot);
     if (!(S.h >= hmin)) {
       S.status = kSysHmin;
       return false;

@@ -104,6 +104,11 @@ int launch_method(const LaunchArgs* a, hipStream_t s) {
 template <class Prob>
 int launch(const LaunchArgs* a, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  if constexpr (HasGershgorin<Prob>::value && !SigmaFromGershgorin<Prob>::value) {
+    if (a->method == kMethodRkc && a->ctl.sr_method == kSrGershgorin)
+      return a->pilot ? launch_method<WithGershgorin<Prob>, kMethodRkc, true>(a, s)
+                      : launch_method<WithGershgorin<Prob>, kMethodRkc, false>(a, s);
+  }
   if (a->pilot)
     return a->method == kMethodRkck ? launch_method<Prob, kMethodRkck, true>(a, s)
                                     : launch_method<Prob, kMethodRkc, true>(a, s);
@@ -129,6 +134,14 @@ int host_run(const LaunchArgs* a) {
                                kLdsStride +
                            1);
   for (int64_t i = 0; i < a->n; ++i) {
+    if constexpr (HasGershgorin<Prob>::value && !SigmaFromGershgorin<Prob>::value) {
+      if (a->method == kMethodRkc && a->ctl.sr_method == kSrGershgorin) {
+        integrate_system<WithGershgorin<Prob>, kMethodRkc>(a->prm, a->n, i, a->y0, a->y1, a->g,
+                                                           a->ctl, a->status, a->stats,
+                                                           slot.data(), a->carry);
+        continue;
+      }
+    }
     if (a->method == kMethodRkck)
       integrate_system<Prob, kMethodRkck>(a->prm, a->n, i, a->y0, a->y1, a->g, a->ctl, a->status,
                                           a->stats, slot.data(), a->carry);

@@ -8,6 +8,9 @@
 namespace rkmi {
 
 enum : int { kMethodRkck = 0, kMethodRkc = 1 };
+// RKC spectral radius: the nonlinear power method (Appendix) or the Gershgorin
+// bound of the analytic Jacobian (problems with Prob::kGershgorin)
+enum : int { kSrPower = 0, kSrGershgorin = 1 };
 
 // Launch-uniform integration controls, formed on the host.
 struct Ctl {
@@ -20,6 +23,7 @@ struct Ctl {
   int mmax;           // RKC stage cap round(sqrt(rtol / (10 UROUND))), >= 2
   int sr_period;      // spectral radius every sr_period accepted steps (25)
   int sr_itmax;       // power-method iterations (50)
+  int sr_method;      // kSrPower | kSrGershgorin
   int refill;         // persistent schedule: idle lanes that trigger a refill (1..64)
 };
 

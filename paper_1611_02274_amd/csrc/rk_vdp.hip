@@ -22,6 +22,17 @@ struct VdpProblem {
     f[0] = y[1];
     f[1] = L.mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
   }
+  // Gershgorin bound of J = [[0, 1], [-2 mu y0 y1 - 1, mu (1 - y0^2)]]: rows
+  // summed from zero, the maximum by fmax from zero
+  static constexpr bool kGershgorin = true;
+  template <class VI>
+  RKMI_HD static double gershgorin(const Lane& L, const Params&, const VI& y) {
+    const double r0 = (0.0 + fabs(0.0)) + fabs(1.0);
+    const double j10 = -2.0 * L.mu * y[0] * y[1] - 1.0;
+    const double j11 = L.mu * (1.0 - y[0] * y[0]);
+    const double r1 = (0.0 + fabs(j10)) + fabs(j11);
+    return fmax(fmax(0.0, r0), r1);
+  }
   // vector-Jacobian products, theta = mu: jtu = J(y)^T u, th += (df/dmu)^T u
   static constexpr int kNTheta = 1;
   template <class VI, class VU, class VO>

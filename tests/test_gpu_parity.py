@@ -78,6 +78,50 @@ def test_vdp_rkc_stiff_many_stages(rk, orc, schedule):
     _case(rk, orc, "rkc", "vdp_stiff", 1000, 13, 0.0, 1.0, 1e-6, 1e-8, schedule=schedule)
 
 
+@pytest.mark.parametrize("problem,n,schedule,cost_order", [
+    ("vdp_stiff", 1000, 1, 0), ("vdp", 777, 2, 0), ("net13", 4133, 1, 0), ("net13", 4133, 2, 0),
+    ("net13", 2000, 1, 1), ("net9", 1000, 0, 0)])
+def test_rkc_gershgorin(rk, orc, problem, n, schedule, cost_order):
+    """RKC with the Gershgorin bound of the analytic Jacobian in place of the
+    power method equals the oracle bit for bit under every schedule."""
+    import torch
+    say(f"case gershgorin {problem} n={n} schedule={schedule} cost_order={cost_order}")
+    if problem.startswith("vdp"):
+        y0, g = I.vdp_inputs(n, 13, (300.0, 3000.0) if problem == "vdp_stiff" else (0.5, 2.0))
+        prob, pb = rk.Problem.vdp(), orc.vdp(orc.SR_GERSHGORIN)
+        t1, rtol, atol = 1.0, 1e-6, 1e-8
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, 2002, (900.0, 2800.0))
+        prob, pb = rk.Problem.network(net), orc.network(net, orc.SR_GERSHGORIN)
+        t1, rtol, atol = 1e-6, 1e-8, 1e-12
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    y1, st, stats = rk.integrate_rkc(prob, yd, gd, 0.0, t1, rtol, atol, sr_method="gershgorin",
+                                     schedule=schedule, cost_order=cost_order)
+    torch.cuda.synchronize()
+    yo, so, sto = orc.rkc_batch(pb, y0, g, 0.0, t1, rtol, atol)
+    compare(y1.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy(), yo, so, sto, atol,
+            f"gershgorin {problem}")
+    assert np.all(sto[4] == 0)
+
+
+def test_gershgorin_rejected_without_a_jacobian(rk):
+    """Problems without an analytic Jacobian and taped integrations refuse the
+    option (RK_EUNSUPPORTED) rather than falling back."""
+    import torch
+    y0, _ = I.pleiades_inputs(4, 6006)
+    yd = torch.from_numpy(y0).cuda()
+    with pytest.raises(RuntimeError):
+        rk.integrate_rkc(rk.Problem.pleiades(), yd, None, 0.0, 0.1, 1e-8, 1e-10,
+                         sr_method="gershgorin")
+    net = I.network_of("net53")
+    y0, g = I.kinetics_inputs(net, 4, 1, (900.0, 2800.0))
+    with pytest.raises(RuntimeError):
+        rk.integrate_rkc(rk.Problem.network(net), torch.from_numpy(y0).cuda(),
+                         torch.from_numpy(g).cuda(), 0.0, 1e-7, 1e-8, 1e-12,
+                         sr_method="gershgorin")
+
+
 def test_vdp_rkck_loose_and_tight(rk, orc):
     _case(rk, orc, "rkck", "vdp", 777, 5, 0.0, 3.0, 1e-5, 0.0)
     _case(rk, orc, "rkck", "vdp", 777, 6, 0.0, 3.0, 1e-11, 1e-13)

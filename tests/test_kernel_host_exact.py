@@ -84,6 +84,40 @@ def test_host_build_of_kernels_equals_oracle(orc, method, problem, n, seed, t0, 
         assert sto[5].min() <= 32 < sto[5].max()
 
 
+@pytest.mark.parametrize("problem,n,seed,t1,rtol,atol", [
+    ("vdp", 64, 13, 1.0, 1e-6, 1e-8), ("vdp_stiff", 32, 14, 1.0, 1e-6, 1e-8),
+    ("net9", 48, 77, 1e-6, 1e-8, 1e-12), ("net13", 48, 2002, 1e-6, 1e-8, 1e-12)])
+def test_host_build_gershgorin_equals_oracle(orc, problem, n, seed, t1, rtol, atol):
+    """RKC with the Gershgorin bound in place of the power method: the host
+    build of the kernels equals the oracle bit for bit."""
+    import paper_1611_02274_amd as rk
+    from paper_1611_02274_amd import _lib
+    if problem.startswith("vdp"):
+        y0, g = I.vdp_inputs(n, seed, (300.0, 3000.0) if problem == "vdp_stiff" else (0.5, 2.0))
+        prob, pb = rk.Problem.vdp(), orc.vdp(orc.SR_GERSHGORIN)
+    else:
+        net = I.network_of(problem)
+        y0, g = I.kinetics_inputs(net, n, seed, (900.0, 2800.0))
+        prob, pb = rk.Problem.network(net), orc.network(net, orc.SR_GERSHGORIN)
+    f = _lib.lib().rkmi_test_host_integrate_sr
+    f.argtypes = [C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                  C.c_int64, C.c_int32]
+    f.restype = C.c_int
+    y0 = np.ascontiguousarray(y0)
+    g = np.ascontiguousarray(g)
+    yh = np.zeros_like(y0)
+    sh = np.zeros(n, dtype=np.int32)
+    sth = np.zeros((6, n), dtype=np.int32)
+    assert f(1, prob.handle, n, y0.ctypes.data, yh.ctypes.data, g.ctypes.data, 0.0, t1, rtol,
+             atol, sh.ctypes.data, sth.ctypes.data, 0, 1) == 0
+    yo, so, sto = orc.rkc_batch(pb, y0, g, 0.0, t1, rtol, atol)
+    assert np.array_equal(sh, so)
+    assert np.array_equal(sth, sto)
+    assert np.array_equal(yh.view(np.int64), yo.view(np.int64))
+    assert np.all(sto[4] == 0) and np.all(sto[3] >= 1)
+
+
 def test_host_build_max_steps(orc):
     import paper_1611_02274_amd as rk
     net = I.network_of("net13")
