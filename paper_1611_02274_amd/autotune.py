@@ -79,6 +79,8 @@ NETWORK_CANDIDATES = (
     dict(schedule=1),                                   # plain, one lane per system
     dict(schedule=2, refill=8), dict(schedule=2, refill=16), dict(schedule=2, refill=32),
     dict(schedule=3, refill=16), dict(schedule=3, refill=32),   # group (large networks)
+    # systems handed out in decreasing cost (a loose-tolerance pilot ranks them)
+    dict(schedule=1, cost_order=1), dict(schedule=2, refill=16, cost_order=1),
 )
 
 
@@ -100,7 +102,8 @@ def tune_network(problem, method: str, y0, g, t0, t1, rtol, atol, fraction=0.05,
     fn = integrate_rkck if method == "rkck" else integrate_rkc
     out = torch.empty_like(ys)
     cands = [c for c in NETWORK_CANDIDATES
-             if c["schedule"] != 3 or problem.n_eq > 16]
+             if (c["schedule"] != 3 or problem.n_eq > 16) and (not c.get("cost_order") or
+                                                               c["schedule"] != 3)]
     times = []
     for c in cands:
         times.append(_time(lambda: fn(problem, ys, gs, t0, t1, rtol, atol, out=out, **c)))
