@@ -70,10 +70,15 @@ def cpu_baseline(w, net, y0, g, target_s: float, sr_method: int = 0):
             ys, _, _ = fn(pb, ys, gs, w.t0 + k * dt, w.t0 + (k + 1) * dt, w.rtol, w.atol)
         return len(idx), time.perf_counter() - t
 
-    m, dt = run(min(w.n, max(64, 8 * cores)))
-    if dt < target_s and m < w.n:
+    # a calibration sample large enough to average over the systems' costs and
+    # the threads, then the sample sized to about target_s (once more if it fell
+    # short of two thirds of that)
+    m, dt = run(min(w.n, max(64, 64 * cores)))
+    for _ in range(2):
+        if dt >= 0.66 * target_s or m >= w.n:
+            break
         want = int(m * target_s / max(dt, 1e-6))
-        m, dt = run(min(w.n, max(m, want)))
+        m, dt = run(min(w.n, max(m + 1, want)))
     return {"value": m / dt, "unit": "systems/s", "cores": cores, "kind": "oracle",
             "sample": f"{m} of {w.n} systems (evenly spaced), {dt:.1f} s on {cores} threads"}
 
