@@ -296,8 +296,11 @@ int rk_integrate_rkck_taped(rk_problem p, int64_t n_sys, const double *y0, doubl
                             void *stream);
 
 /* Workspace bytes of rk_adjoint_rkc: per system max_stages stage records of
- * N + 4 doubles and ckpt_every states (0 on bad arguments).  max_stages bounds
- * the recorded stage counts (RK_STAT_MAX_STAGES of the forward call). */
+ * N + 4 doubles and ckpt_every states, then the order in which the sweep hands
+ * systems to lanes (decreasing accepted steps, from the tape: seven int32 per
+ * system and 32 KiB; results do not depend on it) (0 on bad arguments).
+ * max_stages bounds the recorded stage counts (RK_STAT_MAX_STAGES of the
+ * forward call). */
 size_t rk_adjoint_workspace_bytes(rk_problem p, int64_t n_sys, int32_t max_stages,
                                   int32_t ckpt_every);
 
@@ -317,7 +320,8 @@ int rk_adjoint_rkc(rk_problem p, int64_t n_sys, const double *g, const void *tap
                    void *stream);
 
 /* Workspace bytes of rk_adjoint_rkck: per system 12 N doubles (the six stage
- * arguments and their adjoints) and ckpt_every states (0 on bad arguments). */
+ * arguments and their adjoints) and ckpt_every states, then the sweep's order
+ * as for rk_adjoint_rkc (0 on bad arguments). */
 size_t rk_adjoint_rkck_workspace_bytes(rk_problem p, int64_t n_sys, int32_t ckpt_every);
 
 /* Reverse sweep over a tape from rk_integrate_rkck_taped; arguments as for

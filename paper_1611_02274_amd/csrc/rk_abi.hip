@@ -509,7 +509,8 @@ namespace {
 
 // Adjoint workspace: per 64 systems one block of per-lane columns (RKC:
 // max_stages stage records of N + 4 doubles; RKCK: the six stage arguments and
-// their adjoints, 12 N doubles), plus ckpt_every step-start states.
+// their adjoints, 12 N doubles), plus ckpt_every step-start states; then the
+// order in which the reverse sweep hands systems to lanes (order_layout).
 size_t adjoint_ws_bytes(int method, rk_problem p, int64_t n_sys, int32_t max_stages,
                         int32_t ckpt_every) {
   if (!p || n_sys <= 0 || ckpt_every < 1) return 0;
@@ -518,7 +519,9 @@ size_t adjoint_ws_bytes(int method, rk_problem p, int64_t n_sys, int32_t max_sta
   const int64_t per = method == rkmi::kMethodRkck ? 12 * (int64_t)p->n_eq
                                                   : (int64_t)max_stages * (p->n_eq + 4);
   const int64_t rows = per + (int64_t)ckpt_every * p->n_eq;
-  return (size_t)(blocks * rows * rkmi::kLdsStride * (int64_t)sizeof(double));
+  return rkmi::order_layout((size_t)(blocks * rows * rkmi::kLdsStride * (int64_t)sizeof(double)),
+                            n_sys)
+      .bytes;
 }
 
 int adjoint(int method, rk_problem p, int64_t n_sys, const double* g, const void* tape,

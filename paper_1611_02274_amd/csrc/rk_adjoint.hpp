@@ -30,6 +30,7 @@
 #pragma once
 
 #include "rk_launch.hpp"
+#include "rk_order.hpp"
 
 namespace rkmi {
 
@@ -392,10 +393,12 @@ __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Para
                                                              double* __restrict__ dy0,
                                                              double* __restrict__ dth,
                                                              int32_t* __restrict__ status,
-                                                             double* cols) {
+                                                             double* cols,
+                                                             const int32_t* __restrict__ order) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
-  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
-  if (i >= n) return;
+  const int64_t q = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
+  if (q >= n) return;
+  const int64_t i = order ? (int64_t)order[q] : q;   // lane q sweeps system order[q]
   double* const col = cols +
                       (int64_t)blockIdx.x * adjoint_rows<Prob, Method>(max_stages, T.K) * kLdsStride +
                       threadIdx.x;
@@ -407,11 +410,24 @@ __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Para
   if (status) status[i] = st;
 }
 
-// Bytes of adjoint workspace for n systems (one column block per 64 systems).
+// Bytes of the adjoint's per-lane columns for n systems (one block per 64
+// systems); the workspace holds them followed by an order_layout.
 template <class Prob, int Method>
-int64_t adjoint_workspace_bytes(int64_t n, int max_stages, int K) {
+int64_t adjoint_column_bytes(int64_t n, int max_stages, int K) {
   const int64_t blocks = (n + kLdsStride - 1) / kLdsStride;
   return blocks * adjoint_rows<Prob, Method>(max_stages, K) * kLdsStride * (int64_t)sizeof(double);
+}
+
+// The reverse sweep hands systems to lanes in decreasing order of their
+// accepted steps, read from the tape (the sweep's cost is proportional to
+// them): the cost order with exact keys and no pilot.
+template <int = 0>
+__global__ void adjoint_keys_kernel(const int32_t* __restrict__ count, int64_t n,
+                                    int32_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  keys[(int64_t)kStAccept * n + i] = count[i] > 0 ? count[i] : 0;
+  keys[(int64_t)kStReject * n + i] = 0;
 }
 
 template <class Prob>
@@ -443,19 +459,34 @@ int launch_adjoint(const AdjointArgs* a, void* stream) {
       a->tape.tape_bytes < tape_layout(a->n, a->tape.cap, a->tape.K, Prob::N).bytes)
     return kLaunchInvalid;
   const bool ck = a->method == kMethodRkck;
-  const int64_t need = ck ? adjoint_workspace_bytes<Prob, kMethodRkck>(a->n, 0, a->tape.K)
-                          : adjoint_workspace_bytes<Prob, kMethodRkc>(a->n, a->max_stages,
-                                                                      a->tape.K);
-  if ((!ck && a->max_stages < 2) || !a->ws || a->ws_bytes < (size_t)need) return kLaunchWorkspace;
+  const int64_t cols = ck ? adjoint_column_bytes<Prob, kMethodRkck>(a->n, 0, a->tape.K)
+                          : adjoint_column_bytes<Prob, kMethodRkc>(a->n, a->max_stages,
+                                                                   a->tape.K);
+  if (a->n > 0x7fffffffLL) return kLaunchInvalid;
+  const OrderLayout L = order_layout((size_t)cols, a->n);
+  if ((!ck && a->max_stages < 2) || !a->ws || a->ws_bytes < L.bytes) return kLaunchWorkspace;
   const TapeView T = tape_view(a->tape, a->n, Prob::N);
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* const ws = static_cast<unsigned char*>(a->ws);
+  int32_t* const keys = reinterpret_cast<int32_t*>(ws + L.stats);
+  int32_t* const order = reinterpret_cast<int32_t*>(ws + L.order);
+  int32_t* const hist = reinterpret_cast<int32_t*>(ws + L.hist);
+  int32_t* const offs = reinterpret_cast<int32_t*>(ws + L.offs);
+  const unsigned chunks = (unsigned)((a->n + kOrderChunk - 1) / kOrderChunk);
+  adjoint_keys_kernel<><<<dim3((unsigned)((a->n + 255) / 256)), dim3(256), 0, s>>>(T.count, a->n,
+                                                                                   keys);
+  order_clear_kernel<><<<1, 256, 0, s>>>(hist);
+  order_hist_kernel<><<<chunks, kOrderChunkThreads, 0, s>>>(keys, a->n, hist);
+  order_scan_kernel<><<<1, kOrderScanThreads, 0, s>>>(hist, offs);
+  order_scatter_kernel<><<<chunks, kOrderChunkThreads, 0, s>>>(keys, a->n, offs, order);
   if (ck)
     adjoint_kernel<Prob, kMethodRkck><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
-        a->prm, a->n, a->g, T, 0, a->w, a->dy0, a->dth, a->status, static_cast<double*>(a->ws));
+        a->prm, a->n, a->g, T, 0, a->w, a->dy0, a->dth, a->status, static_cast<double*>(a->ws),
+        order);
   else
     adjoint_kernel<Prob, kMethodRkc><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
         a->prm, a->n, a->g, T, a->max_stages, a->w, a->dy0, a->dth, a->status,
-        static_cast<double*>(a->ws));
+        static_cast<double*>(a->ws), order);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 
