@@ -100,8 +100,9 @@ typedef struct {
                            many of its 64 lanes are idle (1..64; <= 0: tuned default) */
   int32_t cost_order;   /* nonzero: hand systems to lanes in decreasing order of their cost,
                            estimated by a pilot integration at loosened tolerances (see
-                           RK_SCHED_* below); results are unchanged.  Not for taped
-                           integrations or batches (RK_EUNSUPPORTED). */
+                           RK_SCHED_* below); results are unchanged.  Taped
+                           integrations work in the tape's own order area; not for
+                           batches (RK_EUNSUPPORTED). */
   int32_t sr_method;    /* RKC spectral radius: 0 the nonlinear power method (Appendix),
                            1 the Gershgorin bound max_k sum_i |J_ki| of the analytic
                            Jacobian (the Appendix's circle-theorem alternative; van der Pol
@@ -267,6 +268,7 @@ int rk_integrate_rkc_carry(rk_problem p, int64_t n_sys, const double *y0, double
  * K = ckpt_every:
  *   int32 count[n]          (-1: more than C accepted steps; no gradient)
  *   double h[C][n], int32 s[C][n], double y[C / K + 1][N][n]
+ *   the cost order's working area (seven int32 per system and 32 KiB)
  * each array starting on a 256-byte boundary.  The reverse call recomputes
  * each segment of K steps from its checkpoint and each step's stages, and
  * carries lambda = dL/dy(t1) back to dL/dy(t0).  The same n_sys, g,

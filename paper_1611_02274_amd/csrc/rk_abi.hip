@@ -198,8 +198,6 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
         (!p->gershgorin || tape))
       return fail(RK_EUNSUPPORTED, "the Gershgorin bound needs the analytic Jacobian (van der "
                   "Pol, isothermal networks of up to 16 species) and no tape");
-    if (opt->cost_order && tape)
-      return fail(RK_EUNSUPPORTED, "cost_order is not available for a taped integration");
   }
   if (n == 0) return RK_OK;
   int rc;
@@ -231,7 +229,21 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
   a.carry = carry;
   if ((rc = problem_device_data(p, &a.prm))) return rc;
-  if (opt && opt->cost_order) {
+  if (opt && opt->cost_order && tape) {
+    // the pilot (one-lane plain kernel) and the sort work in the tape's own
+    // order area; the taped kernel then takes the order map
+    const rkmi::TapeLayout tl = rkmi::tape_layout(n, tape->cap, tape->K, p->n_eq);
+    rkmi::LaunchArgs t = a;
+    t.schedule = rkmi::kSchedPlain;
+    t.ws = static_cast<unsigned char*>(tape->tape) + tl.off_order;
+    t.ws_bytes = tape->tape_bytes - tl.off_order;
+    rc = rkmi::launch_cost_ordered(
+        &t, 0,
+        [&](const rkmi::LaunchArgs* la, void* st) {
+          return la->pilot ? p->launch(la, st) : p->taped(la, tape, st);
+        },
+        stream);
+  } else if (opt && opt->cost_order) {
     const int64_t base = p->workspace(method, a.schedule, n);
     if (base < 0) return fail(RK_EHIP, "could not query the current device");
     rc = rkmi::launch_cost_ordered(&a, (size_t)base, p->launch, stream);

@@ -38,8 +38,9 @@ enum : int32_t { kSysTape = 4 };
 
 // Tape layout for n systems, cap steps, period K, N unknowns:
 //   count int32 [n] | h double [cap][n] | s int32 [cap][n] | y double [cap/K + 1][N][n]
+//   | the cost order's working area (an order_layout from off_order)
 struct TapeLayout {
-  size_t off_h, off_s, off_ckpt, bytes;
+  size_t off_h, off_s, off_ckpt, off_order, bytes;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -49,7 +50,9 @@ inline TapeLayout tape_layout(int64_t n, int64_t cap, int32_t K, int N) {
   t.off_h = align256(sizeof(int32_t) * (size_t)n);
   t.off_s = t.off_h + align256(sizeof(double) * (size_t)cap * (size_t)n);
   t.off_ckpt = t.off_s + align256(sizeof(int32_t) * (size_t)cap * (size_t)n);
-  t.bytes = t.off_ckpt + sizeof(double) * (size_t)(cap / K + 1) * (size_t)N * (size_t)n;
+  t.off_order = align256(t.off_ckpt + sizeof(double) * (size_t)(cap / K + 1) * (size_t)N *
+                                           (size_t)n);
+  t.bytes = t.off_order + order_layout(0, n).bytes;
   return t;
 }
 
@@ -378,10 +381,12 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void taped_kernel(
                                                            const double* __restrict__ g, Ctl c,
                                                            int32_t* __restrict__ status,
                                                            int32_t* __restrict__ stats,
-                                                           TapeView T) {
+                                                           TapeView T,
+                                                           const int32_t* __restrict__ order) {
   __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
-  const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
-  if (i >= n) return;
+  const int64_t q = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
+  if (q >= n) return;
+  const int64_t i = order ? (int64_t)order[q] : q;   // lane q integrates system order[q]
   taped_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats, T, lds + threadIdx.x);
 }
 
@@ -443,10 +448,10 @@ int launch_taped(const LaunchArgs* a, const TapeArgs* t, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (a->method == kMethodRkck)
     taped_kernel<Prob, kMethodRkck><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
-        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T);
+        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T, a->order);
   else
     taped_kernel<Prob, kMethodRkc><<<dim3((unsigned)blocks), dim3(kLdsStride), 0, s>>>(
-        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T);
+        a->prm, a->n, a->y0, a->y1, a->g, a->ctl, a->status, a->stats, T, a->order);
   return hipGetLastError() == hipSuccess ? kLaunchOk : kLaunchHip;
 }
 

@@ -250,3 +250,30 @@ def test_rkck_autograd_and_fd(rk, orc):
                        for j in cols])
         assert _rel(gy[:, i], fy) <= 1e-6
         assert _rel(ga[cols, i], fa) <= 1e-6
+
+
+@pytest.mark.parametrize("method", ["rkc", "rkck"])
+def test_taped_cost_order_changes_nothing(rk, method):
+    """The taped forward with the cost order (pilot and sort in the tape's own
+    working area) records the same tape and gives the same gradients bit for
+    bit as the forward in system order."""
+    import torch
+    say(f"case taped cost order {method}")
+    net = I.network_of("net13")
+    n, t1 = 3000, (3e-7 if method == "rkc" else 5e-8)
+    y0, g = I.kinetics_inputs(net, n, 5007, (1000.0, 2500.0))
+    w = torch.from_numpy(I.adjoint_weights(net.n_sp, n, 5007)).cuda()
+    prob = rk.Problem.network(net)
+    yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
+    taped = rk.integrate_rkc_taped if method == "rkc" else rk.integrate_rkck_taped
+    adj = rk.adjoint_rkc if method == "rkc" else rk.adjoint_rkck
+    outs = []
+    for co in (0, 1):
+        y1, st, stats, tape = taped(prob, yd, gd, 0.0, t1, 1e-8, 1e-12, max_accepted=2048,
+                                    ckpt_every=16, cost_order=co)
+        dy0, dth, ast = adj(prob, gd, tape, w)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (y1, st, stats, tape.count, dy0, dth, ast)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    assert np.all(outs[0][6] == 0)
