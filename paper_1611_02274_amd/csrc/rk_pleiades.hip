@@ -61,9 +61,25 @@ struct PleiadesProblem {
 
 // Group variant: lane r < 7 of a group of eight holds body r's unknowns
 // (x_r, y_r, x_r', y_r') in registers; lane 7 holds none.  An evaluation
-// writes the positions to the group's LDS area, and each body's lane forms its
-// pair terms and sums in the one-lane order (the pair value of (i, j) is the
-// same bits in the lanes of i and of j), so results equal the one-lane kernels.
+// writes the positions to the group's LDS area; the 21 pair values
+// 1 / (d2 sqrt(d2)) are formed once each, three per lane (pair p by lane p mod
+// 7, with the smaller body index first as the one-lane code forms them), and
+// stored for both orders; each body's lane then sums its terms in the one-lane
+// order, so results equal the one-lane kernels.
+struct PleiadesPairs {
+  int i[21], j[21];
+  constexpr PleiadesPairs() : i(), j() {
+    int p = 0;
+    for (int a = 0; a < 7; ++a)
+      for (int b = a + 1; b < 7; ++b) {
+        i[p] = a;
+        j[p] = b;
+        ++p;
+      }
+  }
+};
+inline constexpr PleiadesPairs kPleiadesPairs{};
+
 struct PleiadesGroup {
   static constexpr int N = 28;
   static constexpr int NR = 0;
@@ -74,7 +90,8 @@ struct PleiadesGroup {
   static constexpr int S = 4;
   static constexpr bool kOwnRhs = true;
   static constexpr int kOffPos = 0;               // x_1..x_7, y_1..y_7
-  static constexpr int kOffRed = 14;              // norm scratch, N doubles
+  static constexpr int kOffPair = 14;             // 1 / r_ij at i * 7 + j
+  static constexpr int kOffRed = kOffPair + 49;   // norm scratch, N doubles
   static constexpr int kLdsPerSystem = kOffRed + N;
   static constexpr int kSp[S * kL] = {0,  1,  2,  3,  4,  5,  6,  -1,     // x_r
                                       7,  8,  9,  10, 11, 12, 13, -1,     // y_r
@@ -87,10 +104,24 @@ struct PleiadesGroup {
   __device__ static void rhs(const Lane&, const Grp<PleiadesGroup>& x, const double (&y)[S],
                              double (&f)[S]) {
     double* const P = x.lds + kOffPos;
+    double* const R = x.lds + kOffPair;
     const bool body = x.r < 7;
     if (body) {
       P[x.r] = y[0];
       P[7 + x.r] = y[1];
+    }
+    group_sync();
+    if (body) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int p = x.r + 7 * t;
+        const int a = kPleiadesPairs.i[p], b = kPleiadesPairs.j[p];
+        const double xa = P[a], xb = P[b], ya = P[7 + a], yb = P[7 + b];
+        const double d2 = (xa - xb) * (xa - xb) + (ya - yb) * (ya - yb);
+        const double rinv = 1.0 / (d2 * sqrt(d2));
+        R[a * 7 + b] = rinv;
+        R[b * 7 + a] = rinv;
+      }
     }
     group_sync();
     double ax = 0.0, ay = 0.0;
@@ -98,12 +129,10 @@ struct PleiadesGroup {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
         if (j == x.r) continue;
-        const double xj = P[j], yj = P[7 + j];
-        const double d2 = (y[0] - xj) * (y[0] - xj) + (y[1] - yj) * (y[1] - yj);
-        const double rinv = 1.0 / (d2 * sqrt(d2));
+        const double rinv = R[x.r * 7 + j];
         const double mj = (double)(j + 1);
-        ax += (mj * (xj - y[0])) * rinv;
-        ay += (mj * (yj - y[1])) * rinv;
+        ax += (mj * (P[j] - y[0])) * rinv;
+        ay += (mj * (P[7 + j] - y[1])) * rinv;
       }
     }
     f[0] = body ? y[2] : 0.0;
