@@ -75,18 +75,20 @@ __device__ double group_sum(const Grp<GP>& x, const double (&t)[GP::S]) {
   return s;
 }
 
-// max_k t_k in order with fmax (t_k >= 0 or NaN).
+// max(0, max_k t_k) with fmax, t_k >= +0 or NaN: the largest non-NaN value (or
+// 0), which no order of the fmax operations changes.  Each lane folds its owned
+// slots from 0 (so no partial result is NaN), then the group's lanes combine
+// in a butterfly of register exchanges (the group is kL aligned lanes, kL a
+// power of two, and reaches this point together).
 template <class GP>
 __device__ double group_fmax(const Grp<GP>& x, const double (&t)[GP::S]) {
-  double* red = x.lds + GP::kOffRed;
+  static_assert((GP::kL & (GP::kL - 1)) == 0 && GP::kL <= 64, "group width");
+  double s = 0.0;
 #pragma unroll
   for (int m = 0; m < GP::S; ++m)
-    if (owns<GP>(x, m)) red[x.sp[m]] = t[m];
-  group_sync();
-  double s = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < GP::N; ++k) s = fmax(s, red[k]);
-  group_sync();
+    if (owns<GP>(x, m)) s = fmax(s, t[m]);
+#pragma unroll
+  for (int o = 1; o < GP::kL; o <<= 1) s = fmax(s, __shfl_xor(s, o, GP::kL));
   return s;
 }
 
