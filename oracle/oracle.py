@@ -97,6 +97,13 @@ def lib():
             "orc_rkc_batch_carry": (C.c_int, [P, C.c_int64, _dp, _dp, _dp, C.c_double,
                                               C.c_double, C.c_double, C.c_double, C.c_int64,
                                               _ip, _ip, _dp, C.c_int]),
+            "orc_rkc_solve_trace": (C.c_int, [P, _dp, _dp, _dp, C.c_double, C.c_double,
+                                              C.c_double, C.c_double, C.c_int64, _ip,
+                                              C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+            "orc_rkc_replay_jvp_cs": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _ip,
+                                                _dp, _dp, _dp, _dp]),
+            "orc_rkck_replay_jvp_cs": (C.c_int, [P, _dp, _dp, C.c_double, C.c_int64, _dp, _dp,
+                                                 _dp, _dp, _dp]),
             "orc_max_threads": (C.c_int, []),
             "orc_cr_exp": (C.c_double, [C.c_double]),
             "orc_cr_log": (C.c_double, [C.c_double]),
@@ -322,6 +329,51 @@ def rkc_solve(pb, g, y0, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, rec_ca
     assert rc >= 0, rc
     n = min(nrec.value, rec_cap)
     return y1, rc, st, rh[:n].copy(), rs[:n].copy()
+
+
+# One attempted RKC step (orc_rkc_attempt).
+ATTEMPT = np.dtype([("t", np.float64), ("h_want", np.float64), ("h", np.float64),
+                    ("sigma", np.float64), ("err", np.float64), ("nstep", np.int64),
+                    ("n_sr", np.int64), ("m", np.int32), ("accepted", np.int32)])
+
+
+def rkc_trace(pb, g, y0, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, cap=1 << 18):
+    """RKC as rkc_solve; returns (y1, status, stats, trace) with one record of
+    ATTEMPT per attempted step."""
+    y0 = _vec(y0, pb.n_eq)
+    y1 = np.zeros(pb.n_eq)
+    st = np.zeros(NSTATS, dtype=np.int32)
+    tr = np.zeros(cap, dtype=ATTEMPT)
+    n = C.c_int64(0)
+    rc = lib().orc_rkc_solve_trace(pb.ptr, _d(_g(pb, g)), _d(y0), _d(y1), t0, t1, rtol, atol,
+                                   max_steps, _i(st), tr.ctypes.data_as(C.c_void_p), cap,
+                                   C.byref(n))
+    assert rc >= 0, rc
+    assert n.value <= cap
+    return y1, rc, st, tr[:n.value].copy()
+
+
+def rkc_replay_jvp_cs(pb, g, y0, t0, h, s, w, dy0, dtheta=None):
+    """Complex-step derivative of w . y(t1) along (dy0, dtheta) for the replayed
+    RKC steps (h, s)."""
+    y0, w, dy0, h = _vec(y0, pb.n_eq), _vec(w, pb.n_eq), _vec(dy0, pb.n_eq), _vec(h)
+    s = np.ascontiguousarray(s, dtype=np.int32)
+    dth = _vec(dtheta, pb.n_theta) if dtheta is not None else None
+    out = C.c_double()
+    assert lib().orc_rkc_replay_jvp_cs(pb.ptr, _d(_g(pb, g)), _d(y0), t0, h.size, _d(h), _i(s),
+                                       _d(w), _d(dy0), _d(dth), C.byref(out)) == 0
+    return out.value
+
+
+def rkck_replay_jvp_cs(pb, g, y0, t0, h, w, dy0, dtheta=None):
+    """Complex-step derivative of w . y(t1) along (dy0, dtheta) for the replayed
+    RKCK steps h."""
+    y0, w, dy0, h = _vec(y0, pb.n_eq), _vec(w, pb.n_eq), _vec(dy0, pb.n_eq), _vec(h)
+    dth = _vec(dtheta, pb.n_theta) if dtheta is not None else None
+    out = C.c_double()
+    assert lib().orc_rkck_replay_jvp_cs(pb.ptr, _d(_g(pb, g)), _d(y0), t0, h.size, _d(h),
+                                        _d(w), _d(dy0), _d(dth), C.byref(out)) == 0
+    return out.value
 
 
 def rkck_solve_rec(pb, g, y0, t0, t1, rtol, atol, max_steps=DEFAULT_MAX_STEPS, rec_cap=1 << 20):

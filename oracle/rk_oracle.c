@@ -10,6 +10,7 @@
  */
 #include "rk_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <quadmath.h>
 #include <stdlib.h>
@@ -917,19 +918,129 @@ double orc_rkc_accept_factor(double err, double err_prev, double h, double h_pre
   return fac;
 }
 
-/* RKC driver (Sec. 3.2 listing, Sec. 2.2 equations).
+/* ------------------------------------------------------- RKC controller parts
+ * Each part of the RKC step-size and stage control of Sec. 2.2, as its own
+ * function; the driver below combines them in the order of Sec. 3.2. */
+
+/* Weighted RMS norm of Eq. E:rmsE: ||d / (T sqrt(N))||_2 with per-component
+ * weights T = w, i.e. sqrt((1/N) sum_i (d_i / w_i)^2), squares summed in
+ * index order. */
+static double rms_norm(int n, const double *d, const double *w) {
+  double e = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double q = d[i] / w[i];
+    e += q * q;
+  }
+  return sqrt(e / (double)n);
+}
+
+/* A step size held within [hMin, hMax]. */
+static double clamp_step(double h, double hmin, double hmax) {
+  return fmax(hmin, fmin(hmax, h));
+}
+
+/* The step is stretched to reach t1 when t1 lies within 10% beyond it (the
+ * driver of Sec. 3.2), so no sliver of a step is left at the end. */
+static double stretch_to_end(double h, double t, double t1) {
+  return (1.1 * h >= fabs(t1 - t)) ? fabs(t1 - t) : h;
+}
+
+/* Error of the step y_n -> y_{n+1} (Sec. 2.2):
+ * Delta = 4/5 (y_n - y_{n+1}) + 2/5 h (f_n + f_{n+1}), measured by Eq. E:rmsE
+ * with T = atol + rtol max(|y_n|, |y_{n+1}|). */
+static double rkc_step_error(int n, const double *yn, const double *y, const double *Fn,
+                             const double *F1, double h, double rtol, double atol) {
+  double d[ORC_MAXN], w[ORC_MAXN];
+  for (int i = 0; i < n; ++i) {
+    d[i] = 0.8 * (yn[i] - y[i]) + 0.4 * h * (Fn[i] + F1[i]);
+    w[i] = atol + rtol * fmax(fabs(y[i]), fabs(yn[i]));
+  }
+  return rms_norm(n, d, w);
+}
+
+/* Initial step size (Sec. 2.2).  A tentative forward-Euler step of size
+ * dt0 = 1/sigma is taken from (t0, y0) with f0 = f(t0, y0); its error
+ * Delta_0 = dt0 (f(t0 + dt0, y0 + dt0 f0) - f0) is measured by Eq. E:rmsE, and
+ * the first step is dt1 = 0.1 dt0 / ||Delta_0||^(1/2).
+ * Reading (the text does not bound dt0 or dt1; the driver of Sec. 3.2 does):
+ * dt0 is hMax when sigma hMax <= 1 and at least hMin; dt1 is at least hMin and
+ * is hMax whenever 0.1 dt0 >= hMax ||Delta_0||^(1/2) (the comparison is made
+ * before dividing, so a zero error gives hMax).  The weights are
+ * atol + rtol |y0| (the tentative state is not a solution value), and the norm
+ * is that of f(...) - f0 times dt0, as the listing evaluates it. */
+static double rkc_initial_step(const orc_sys *S, double t0, const double *y0, const double *f0,
+                               double sigma, double hmin, double hmax, double rtol,
+                               double atol) {
+  const int N = S->pb->n_eq;
+  double dt0 = hmax;
+  if (sigma * dt0 > 1.0) dt0 = 1.0 / sigma;
+  dt0 = fmax(dt0, hmin);
+  double z[ORC_MAXN], f1[ORC_MAXN], d[ORC_MAXN], w[ORC_MAXN];
+  for (int i = 0; i < N; ++i) z[i] = y0[i] + dt0 * f0[i];
+  rhs(S, t0 + dt0, z, f1);
+  for (int i = 0; i < N; ++i) {
+    d[i] = f1[i] - f0[i];
+    w[i] = atol + rtol * fabs(y0[i]);
+  }
+  const double err0 = dt0 * rms_norm(N, d, w);
+  if (P1 * dt0 < hmax * sqrt(err0)) return fmax(P1 * dt0 / sqrt(err0), hmin);
+  return hmax;
+}
+
+/* Step after a rejection (Eq. dtnp1 with f = 0.8 / err^(1/3), p = 2).
+ * Reading: as in the driver of Sec. 3.2, without the equation's 0.1 floor (the
+ * two differ only for err > 512).  A non-finite error (which the listing would
+ * accept, NaN > 1 being false) cuts the step by P1, as the RKCK driver does. */
+static double rkc_rejected_step(double err, double h) {
+  return isfinite(err) ? 0.8 * h / orc_cr_pow(err, 1.0 / 3.0) : P1 * h;
+}
+
+/* Step after an accepted step: min(10, max(0.1, f)) h (Eq. dtnp1) with the
+ * factor f of orc_rkc_accept_factor, then held within [hMin, hMax]. */
+static double rkc_next_step(double err, double err_prev, double h, double h_prev, int have_prev,
+                            double hmin, double hmax) {
+  const double fac = orc_rkc_accept_factor(err, err_prev, h, h_prev, have_prev);
+  return clamp_step(h * fmax(P1, fac), hmin, hmax);
+}
+
+/* Spectral radius of df/dy at (t, y_n) (Sec. 2.2, Appendix): the nonlinear
+ * power method with the stored eigenvector estimate v, or the Gershgorin bound
+ * of the analytic Jacobian when the problem asks for it.  Counts the call, its
+ * iterations and their right-hand-side evaluations. */
+static double rkc_sigma(const orc_sys *S, double t, const double *yn, const double *Fn,
+                        double hmax, double *v, int64_t *n_sr, int64_t *n_pow, int64_t *n_rhs) {
+  (*n_sr)++;
+  if (S->pb->sr_method == 1) return gershgorin(S, yn, NULL);
+  int it = 0;
+  const double sigma = spec_rad(S, t, yn, Fn, hmax, v, 50, &it);
+  *n_pow += it;
+  *n_rhs += it;
+  return sigma;
+}
+
+/* Accepted steps between refreshes of the spectral radius (Sec. 2.2: every
+ * 25 internal steps, and after every rejected step). */
+#define SR_PERIOD 25
+
+/* RKC driver (Sec. 3.2, with the parts of Sec. 2.2 above).  Each attempt:
+ * stretch the step to the end point if close; refresh sigma at the first step
+ * and every SR_PERIOD accepted steps; on the first attempt choose the initial
+ * step; pick the stage count (which may shorten the step); take the step and
+ * evaluate f at its end; accept (advance, new step from Eq. dtnp1, f_{n+1}
+ * becomes f_n) or reject (smaller step, sigma refreshed).
  * Reading (restart): every call starts fresh, with the previous-step memory
  * cleared and the eigenvector estimate v set to f(t0, y0); the listing's test
  * of a step size below UROUND as "not set yet" is replaced by explicit flags,
  * which agree with it whenever steps exceed UROUND.
- * Reading (error not finite): the listing accepts a NaN error (NaN > 1 is
- * false); here it is rejected with the step cut by P1, as in the RKCK driver.
- * Reading (rejection): the step becomes 0.8 h / err^(1/3) as in the listing,
- * without the 0.1 floor of Eq. dtnp1.
- * Guards as in the RKCK driver. */
+ * Reading (refresh): the refresh at the loop top runs on every attempt made
+ * while the accepted-step count is a multiple of SR_PERIOD, so a rejection at
+ * such a count refreshes sigma twice (after the rejection and at the retry).
+ * Guards as in the RKCK driver.  A trace, when given, receives one record per
+ * attempt. */
 static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *y0, double *y1,
                           double t0, double t1, double rtol, double atol, int64_t max_steps,
-                          int32_t *stats, step_rec *rec, double *carry) {
+                          int32_t *stats, step_rec *rec, double *carry, orc_rkc_attempt *trace,
+                          int64_t trace_cap, int64_t *n_trace) {
   if (check_problem(pb) || !(t1 >= t0) || !(rtol > 0.0) || !(atol >= 0.0)) return -1;
   const int N = pb->n_eq;
   const int mmax = orc_rkc_mmax(rtol);
@@ -940,7 +1051,7 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
     return -2;
   }
   sys_init(S, pb, g);
-  double y_n[ORC_MAXN], F_n[ORC_MAXN], y[ORC_MAXN], F1[ORC_MAXN], v[ORC_MAXN], z[ORC_MAXN];
+  double y_n[ORC_MAXN], F_n[ORC_MAXN], y[ORC_MAXN], F1[ORC_MAXN], v[ORC_MAXN];
   const double hmax = fabs(t1 - t0);
   const double hmin = 10.0 * UROUND * fmax(fabs(t0), hmax);
   double t = t0;
@@ -948,7 +1059,7 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
     y_n[i] = y0[i];
     F_n[i] = 0.0;
   }
-  int64_t n_acc = 0, n_rej = 0, n_rhs = 0, n_sr = 0, n_pow = 0, attempts = 0;
+  int64_t n_acc = 0, n_rej = 0, n_rhs = 0, n_sr = 0, n_pow = 0, attempts = 0, n_tr = 0;
   int max_m = 0, status = ORC_OK;
   if (t < t1) {
     rhs(S, t, y_n, F_n);
@@ -978,75 +1089,40 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
       status = ORC_MAXSTEPS;
       break;
     }
-    /* stretch the step to the end point when it is within 10% of it */
     h_want = h;
-    if (1.1 * h >= fabs(t1 - t)) h = fabs(t1 - t);
-    /* spectral radius at the first step and every 25 accepted steps */
-    if (nstep % 25 == 0) {
-      if (pb->sr_method == 1) {
-        sigma = gershgorin(S, y_n, NULL);
-        n_sr++;
-      } else {
-        int it = 0;
-        sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
-        n_sr++;
-        n_pow += it;
-        n_rhs += it;
-      }
-    }
+    h = stretch_to_end(h, t, t1);
+    if (nstep % SR_PERIOD == 0) sigma = rkc_sigma(S, t, y_n, F_n, hmax, v, &n_sr, &n_pow, &n_rhs);
     if (first) {
-      /* initial step: trial Euler step of size 1/sigma (Sec. 2.2) */
-      h = hmax;
-      if (sigma * h > 1.0) h = 1.0 / sigma;
-      h = fmax(h, hmin);
-      for (int i = 0; i < N; ++i) z[i] = y_n[i] + h * F_n[i];
-      rhs(S, t + h, z, F1);
+      h = rkc_initial_step(S, t, y_n, F_n, sigma, hmin, hmax, rtol, atol);
       n_rhs++;
-      double e = 0.0;
-      for (int i = 0; i < N; ++i) {
-        double est = (F1[i] - F_n[i]) / (atol + rtol * fabs(y_n[i]));
-        e += est * est;
-      }
-      double err0 = h * sqrt(e / (double)N);
-      if (P1 * h < hmax * sqrt(err0))
-        h = fmax(P1 * h / sqrt(err0), hmin);
-      else
-        h = hmax;
       first = 0;
     }
-    int m = orc_rkc_stage_count(h, sigma, mmax, &h);
+    const int m = orc_rkc_stage_count(h, sigma, mmax, &h);
     if (m > max_m) max_m = m;
     tab_fill(&tb, m);
     rkc_step(S, &tb, t, y_n, F_n, h, m, y, NULL);
-    n_rhs += m - 1;
     rhs(S, t + h, y, F1);
-    n_rhs++;
-    /* error estimate 4/5 (y_n - y_{n+1}) + 2/5 h (f_n + f_{n+1}) and its
-     * weighted RMS norm, weights atol + rtol max(|y_n|, |y_{n+1}|) (Eq. E:rmsE) */
-    double e = 0.0;
-    for (int i = 0; i < N; ++i) {
-      double est = 0.8 * (y_n[i] - y[i]) + 0.4 * h * (F_n[i] + F1[i]);
-      est = est / (atol + rtol * fmax(fabs(y[i]), fabs(y_n[i])));
-      e += est * est;
-    }
-    double err = sqrt(e / (double)N);
+    n_rhs += m;
+    const double err = rkc_step_error(N, y_n, y, F_n, F1, h, rtol, atol);
     attempts++;
-    if (err > 1.0 || !isfinite(err)) {
+    const int accept = err <= 1.0;   /* NaN and errors above 1 are rejected */
+    if (trace && n_tr < trace_cap) {
+      orc_rkc_attempt *a = trace + n_tr;
+      a->t = t;
+      a->h_want = h_want;
+      a->h = h;
+      a->sigma = sigma;
+      a->err = err;
+      a->m = m;
+      a->accepted = accept;
+      a->nstep = nstep;
+      a->n_sr = n_sr;
+    }
+    n_tr++;
+    if (!accept) {
       n_rej++;
-      if (isfinite(err))
-        h = 0.8 * h / orc_cr_pow(err, 1.0 / 3.0);
-      else
-        h = P1 * h;
-      if (pb->sr_method == 1) {
-        sigma = gershgorin(S, y_n, NULL);
-        n_sr++;
-      } else {
-        int it = 0;
-        sigma = spec_rad(S, t, y_n, F_n, hmax, v, 50, &it);
-        n_sr++;
-        n_pow += it;
-        n_rhs += it;
-      }
+      h = rkc_rejected_step(err, h);
+      sigma = rkc_sigma(S, t, y_n, F_n, hmax, v, &n_sr, &n_pow, &n_rhs);
       if (!(h >= hmin)) {
         status = ORC_HMIN;
         break;
@@ -1056,8 +1132,8 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
       t += h;
       nstep++;
       n_acc++;
-      double fac = orc_rkc_accept_factor(err, err_prev, h, h_prev, have_prev);
       rec_push(rec, h, m);
+      const double hn = rkc_next_step(err, err_prev, h, h_prev, have_prev, hmin, hmax);
       err_prev = err;
       h_prev = h;
       have_prev = 1;
@@ -1065,14 +1141,14 @@ static int rkc_solve_impl(const orc_problem *pb, const double *g, const double *
         y_n[i] = y[i];
         F_n[i] = F1[i];
       }
-      h = h * fmax(P1, fac);
-      h = fmax(hmin, fmin(hmax, h));
+      h = hn;
       if (!all_finite(N, y_n)) {
         status = ORC_NONFINITE;
         break;
       }
     }
   }
+  if (n_trace) *n_trace = n_tr;
   if (carry) {
     carry[ORC_CARRY_VALID] = status == ORC_OK ? 1.0 : 0.0;
     carry[ORC_CARRY_H] = cut ? h_want : h;
@@ -1102,9 +1178,20 @@ int orc_rkc_solve(const orc_problem *pb, const double *g, const double *y0, doub
                   int32_t *stats, double *rec_h, int32_t *rec_s, int64_t rec_cap,
                   int64_t *n_rec) {
   step_rec r = {rec_h, rec_s, 0, (rec_h && rec_s) ? rec_cap : 0, 0};
-  int st = rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r, NULL);
+  int st = rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, &r, NULL, NULL, 0,
+                          NULL);
   if (n_rec) *n_rec = r.n;
   return st;
+}
+
+/* As orc_rkc_solve without the step record; trace (capacity trace_cap)
+ * receives one record per attempt, *n_trace the number of attempts. */
+int orc_rkc_solve_trace(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                        double t0, double t1, double rtol, double atol, int64_t max_steps,
+                        int32_t *stats, orc_rkc_attempt *trace, int64_t trace_cap,
+                        int64_t *n_trace) {
+  return rkc_solve_impl(pb, g, y0, y1, t0, t1, rtol, atol, max_steps, stats, NULL, NULL, trace,
+                        trace_cap, n_trace);
 }
 
 int orc_rkc_replay(const orc_problem *pb, const double *g, const double *y0, double t0,
@@ -1312,6 +1399,172 @@ int orc_rkck_replay_adjoint(const orc_problem *pb, const double *g, const double
   return 0;
 }
 
+/* ------------------------------------------------------- complex step
+ * Directional derivatives of the replayed step maps for the pins of the
+ * adjoints: the same replay in complex arithmetic, started from
+ * (y0 + i e dy0, theta + i e dtheta); the imaginary part of L over e is the
+ * derivative along (dy0, dtheta) to within O(e^2), with no cancellation. */
+
+#define CS_STEP 1.0e-20
+
+typedef struct {
+  const orc_sys *S;
+  double complex kf[ORC_MAXR], kr[ORC_MAXR];
+  double complex mu;
+} cs_sys;
+
+/* ln A_j + i e dtheta_j scales k_f,j and k_r,j by exp(i e dtheta_j). */
+static void cs_init(cs_sys *Z, const orc_sys *S, const double *dtheta) {
+  const orc_problem *pb = S->pb;
+  Z->S = S;
+  Z->mu = 0.0;
+  if (pb->kind == ORC_VDP) Z->mu = S->g[0] + I * (CS_STEP * (dtheta ? dtheta[0] : 0.0));
+  if (pb->kind == ORC_MASS_ACTION)
+    for (int j = 0; j < pb->n_rx; ++j) {
+      const double th = CS_STEP * (dtheta ? dtheta[j] : 0.0);
+      const double complex e = cos(th) + I * sin(th);
+      Z->kf[j] = S->kf[j] * e;
+      Z->kr[j] = S->kr[j] * e;
+    }
+}
+
+/* The right-hand side of rhs() in complex arithmetic. */
+static void rhs_cs(const cs_sys *Z, const double complex *y, double complex *f) {
+  const orc_problem *pb = Z->S->pb;
+  const int N = pb->n_eq;
+  if (pb->kind == ORC_VDP) {
+    f[0] = y[1];
+    f[1] = Z->mu * (1.0 - y[0] * y[0]) * y[1] - y[0];
+  } else if (pb->kind == ORC_LINEAR) {
+    for (int i = 0; i < N; ++i) {
+      double complex s = 0.0;
+      for (int j = 0; j < N; ++j) s += pb->A[i * N + j] * y[j];
+      f[i] = s;
+    }
+  } else {
+    double complex C[ORC_MAXN], omega[ORC_MAXN], M = 0.0;
+    for (int k = 0; k < N; ++k) C[k] = (Z->S->rho * y[k]) * Z->S->invW[k];
+    for (int k = 0; k < N; ++k) M += C[k];
+    for (int k = 0; k < N; ++k) omega[k] = 0.0;
+    for (int j = 0; j < pb->n_rx; ++j) {
+      const int r0 = pb->reac[2 * j], r1 = pb->reac[2 * j + 1];
+      const int p0 = pb->prod[2 * j], p1 = pb->prod[2 * j + 1];
+      const double complex q = Z->kf[j] * C[r0] * (r1 >= 0 ? C[r1] : M) -
+                               Z->kr[j] * C[p0] * (p1 >= 0 ? C[p1] : M);
+      omega[r0] -= q;
+      if (r1 >= 0) omega[r1] -= q;
+      omega[p0] += q;
+      if (p1 >= 0) omega[p1] += q;
+    }
+    for (int k = 0; k < N; ++k) f[k] = (pb->W[k] * omega[k]) * Z->S->irho;
+  }
+}
+
+static int cs_setup(const orc_problem *pb, const double *g, const double *y0, const double *dy0,
+                    const double *dtheta, orc_sys **S, cs_sys **Z, double complex *y) {
+  if (check_vjp_problem(pb)) return -1;
+  *S = (orc_sys *)malloc(sizeof(orc_sys));
+  *Z = (cs_sys *)malloc(sizeof(cs_sys));
+  if (!*S || !*Z) {
+    free(*S);
+    free(*Z);
+    return -2;
+  }
+  sys_init(*S, pb, g);
+  cs_init(*Z, *S, dtheta);
+  for (int i = 0; i < pb->n_eq; ++i) y[i] = y0[i] + I * (CS_STEP * (dy0 ? dy0[i] : 0.0));
+  return 0;
+}
+
+static double cs_result(int n, const double *w, const double complex *y) {
+  double complex L = 0.0;
+  for (int i = 0; i < n; ++i) L += w[i] * y[i];
+  return cimag(L) / CS_STEP;
+}
+
+int orc_rkc_replay_jvp_cs(const orc_problem *pb, const double *g, const double *y0, double t0,
+                          int64_t n_steps, const double *h, const int32_t *s, const double *w,
+                          const double *dy0, const double *dtheta, double *jvp) {
+  (void)t0;
+  orc_sys *S;
+  cs_sys *Z;
+  double complex y[ORC_MAXN], F[ORC_MAXN], f[ORC_MAXN], wjm1[ORC_MAXN], wjm2[ORC_MAXN],
+      wj[ORC_MAXN];
+  int rc = cs_setup(pb, g, y0, dy0, dtheta, &S, &Z, y);
+  if (rc) return rc;
+  const int N = pb->n_eq;
+  int smax = 2;
+  for (int64_t k = 0; k < n_steps; ++k)
+    if (s[k] > smax) smax = s[k];
+  rkc_tab tb;
+  if (tab_alloc(&tb, smax)) {
+    free(S);
+    free(Z);
+    return -2;
+  }
+  for (int64_t k = 0; k < n_steps; ++k) {
+    const double hk = h[k];
+    tab_fill(&tb, s[k]);
+    rhs_cs(Z, y, F);
+    for (int i = 0; i < N; ++i) {
+      wjm2[i] = y[i];
+      wjm1[i] = y[i] + (tb.mut[1] * hk) * F[i];
+    }
+    for (int j = 2; j <= s[k]; ++j) {
+      rhs_cs(Z, wjm1, f);
+      const double c0 = 1.0 - tb.mu[j] - tb.nu[j];
+      for (int i = 0; i < N; ++i)
+        wj[i] = c0 * y[i] + tb.mu[j] * wjm1[i] + tb.nu[j] * wjm2[i] + (tb.mut[j] * hk) * f[i] +
+                (tb.gt[j] * hk) * F[i];
+      for (int i = 0; i < N; ++i) {
+        wjm2[i] = wjm1[i];
+        wjm1[i] = wj[i];
+      }
+    }
+    for (int i = 0; i < N; ++i) y[i] = wjm1[i];
+  }
+  *jvp = cs_result(N, w, y);
+  tab_free(&tb);
+  free(S);
+  free(Z);
+  return 0;
+}
+
+int orc_rkck_replay_jvp_cs(const orc_problem *pb, const double *g, const double *y0, double t0,
+                           int64_t n_steps, const double *h, const double *w, const double *dy0,
+                           const double *dtheta, double *jvp) {
+  (void)t0;
+  orc_sys *S;
+  cs_sys *Z;
+  double complex y[ORC_MAXN], z[ORC_MAXN], k[6][ORC_MAXN], f[ORC_MAXN];
+  int rc = cs_setup(pb, g, y0, dy0, dtheta, &S, &Z, y);
+  if (rc) return rc;
+  const int N = pb->n_eq;
+  for (int64_t n = 0; n < n_steps; ++n) {
+    const double hk = h[n];
+    rhs_cs(Z, y, f);
+    for (int i = 0; i < N; ++i) k[0][i] = hk * f[i];
+    for (int st = 1; st < 6; ++st) {
+      for (int i = 0; i < N; ++i) {
+        double complex acc = y[i];
+        for (int j = 0; j < st; ++j) acc = acc + RKCK_B[st][j] * k[j][i];
+        z[i] = acc;
+      }
+      rhs_cs(Z, z, f);
+      for (int i = 0; i < N; ++i) k[st][i] = hk * f[i];
+    }
+    for (int i = 0; i < N; ++i) {
+      double complex acc = y[i];
+      for (int st = 0; st < 6; ++st) acc = acc + RKCK_C[st] * k[st][i];
+      y[i] = acc;
+    }
+  }
+  *jvp = cs_result(N, w, y);
+  free(S);
+  free(Z);
+  return 0;
+}
+
 /* ------------------------------------------------------------------ batches */
 
 int orc_max_threads(void) {
@@ -1349,7 +1602,8 @@ static int batch_common(int method, const orc_problem *pb, int64_t n, const doub
     double *cp = carry ? cs : NULL;
     int rc = (method == 0)
                  ? rkck_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL, cp)
-                 : rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL, cp);
+                 : rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, st, NULL, cp, NULL,
+                                  0, NULL);
     if (rc < 0) {
 #pragma omp atomic write
       failed = 1;
@@ -1395,7 +1649,8 @@ int orc_rkc_adjoint_batch(const orc_problem *pb, int64_t n, const double *y0, co
     gather(g, n, i, P, gs);
     gather(w, n, i, N, ws);
     step_rec r = {NULL, NULL, 0, 0, 1};
-    int rc = rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r, NULL);
+    int rc = rkc_solve_impl(pb, gs, ys, yo, t0, t1, rtol, atol, max_steps, NULL, &r, NULL, NULL,
+                            0, NULL);
     int rc2 = (rc >= 0 && r.n <= r.cap)
                   ? orc_rkc_replay_adjoint(pb, gs, ys, t0, r.n, r.h, r.s, ws, d0, dth)
                   : -2;

@@ -131,6 +131,24 @@ int orc_rkc_solve(const orc_problem *pb, const double *g, const double *y0, doub
                   double t0, double t1, double rtol, double atol, int64_t max_steps,
                   int32_t *stats, double *rec_h, int32_t *rec_s, int64_t rec_cap,
                   int64_t *n_rec);
+/* One attempted RKC step, as the driver made it (orc_rkc_solve_trace). */
+typedef struct {
+  double t;        /* time at the start of the attempt */
+  double h_want;   /* step the controller proposed (before the end-point stretch) */
+  double h;        /* step taken (after the stretch, the initial-step rule, the stage cap) */
+  double sigma;    /* spectral radius used for the stage count */
+  double err;      /* weighted RMS error of the attempt */
+  int64_t nstep;   /* accepted steps before the attempt */
+  int64_t n_sr;    /* spectral-radius estimates made so far, this attempt's included */
+  int32_t m;       /* stages */
+  int32_t accepted;
+} orc_rkc_attempt;
+/* As orc_rkc_solve; trace (capacity trace_cap) receives one record per
+ * attempt, *n_trace the number of attempts (may exceed trace_cap). */
+int orc_rkc_solve_trace(const orc_problem *pb, const double *g, const double *y0, double *y1,
+                        double t0, double t1, double rtol, double atol, int64_t max_steps,
+                        int32_t *stats, orc_rkc_attempt *trace, int64_t trace_cap,
+                        int64_t *n_trace);
 /* Replays accepted RKC steps (h_k, s_k) from y0 with no controller. */
 int orc_rkc_replay(const orc_problem *pb, const double *g, const double *y0, double t0,
                    int64_t n_steps, const double *h, const int32_t *s, double *y1);
@@ -146,6 +164,18 @@ int orc_rkck_replay(const orc_problem *pb, const double *g, const double *y0, do
 int orc_rkck_replay_adjoint(const orc_problem *pb, const double *g, const double *y0,
                             double t0, int64_t n_steps, const double *h, const double *w,
                             double *dy0, double *dtheta);
+
+/* Complex-step directional derivatives of L = w . y(t1) along (dy0, dtheta)
+ * for the replayed RKC / RKCK step maps (ORC_VDP, ORC_LINEAR, ORC_MASS_ACTION):
+ * Im L(y0 + i e dy0, theta + i e dtheta) / e with e = 1e-20, every operation of
+ * the replay carried out in complex arithmetic; free of the cancellation of
+ * finite differences.  dtheta has orc_n_theta entries (may be NULL: zero). */
+int orc_rkc_replay_jvp_cs(const orc_problem *pb, const double *g, const double *y0, double t0,
+                          int64_t n_steps, const double *h, const int32_t *s, const double *w,
+                          const double *dy0, const double *dtheta, double *jvp);
+int orc_rkck_replay_jvp_cs(const orc_problem *pb, const double *g, const double *y0, double t0,
+                           int64_t n_steps, const double *h, const double *w, const double *dy0,
+                           const double *dtheta, double *jvp);
 
 /* ---- batches (SoA), OpenMP across systems; n_threads <= 0: runtime default ---- */
 int orc_rkck_batch(const orc_problem *pb, int64_t n, const double *y0, const double *g,
