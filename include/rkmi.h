@@ -225,6 +225,26 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
                      int32_t *status, int32_t *stats, void *ws, size_t ws_bytes,
                      const rk_options *opt, void *stream);
 
+/* RKC integration as rk_integrate_rkc that allocates nothing, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Its workspace is the library's
+ * own device array of RK_SCRATCH_BYTES bytes on each GPU (held from the
+ * library's load until the process ends); a call whose workspace would be
+ * larger (rk_workspace_bytes with the same arguments) returns RK_EWORKSPACE
+ * and enqueues nothing.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (several streams or host threads at once) race, so
+ * serialize them; each call starts from its own cleared queue and order
+ * counters, whatever the previous call left.  The problem's constants must
+ * already be on the current device: the first allocating call with the
+ * problem on that device (any other rk_integrate_* call with n_sys > 0 and
+ * t1 > t0) puts them there; otherwise RK_EINVAL.  Other arguments, layouts,
+ * ownership and errors as rk_integrate_rkc. */
+#define RK_SCRATCH_BYTES (64u << 20)
+int rk_integrate_rkc_noalloc(rk_problem p, int64_t n_sys, const double *y0, double *y1,
+                             const double *g, double t0, double t1, double rtol, double atol,
+                             int32_t *status, int32_t *stats, const rk_options *opt,
+                             void *stream);
+
 /* Controller state carried from one call to the next instead of the restart
  * at every call (Sec. 3 notes that carrying the integrator's data across
  * global steps may perform better where the application allows it).  carry:

@@ -15,6 +15,7 @@ RK_OK, RK_EINVAL, RK_ENOMEM, RK_EHIP, RK_EUNSUPPORTED, RK_EWORKSPACE = 0, -1, -2
 RK_SYS_OK, RK_SYS_NONFINITE, RK_SYS_HMIN, RK_SYS_MAXSTEPS, RK_SYS_TAPE = 0, 1, 2, 3, 4
 RK_NSTATS = 6
 RK_METHOD_RKCK, RK_METHOD_RKC = 0, 1
+RK_SCRATCH_BYTES = 64 << 20   # workspace of rk_integrate_rkc_noalloc per device
 
 EXPORTS = (
     "rk_version", "rk_last_error", "rk_problem_create_vdp", "rk_problem_create_mass_action",
@@ -79,6 +80,10 @@ def lib():
         for name in ("rk_integrate_rkck", "rk_integrate_rkc"):
             getattr(L, name).argtypes = integ
             getattr(L, name).restype = C.c_int
+        L.rk_integrate_rkc_noalloc.argtypes = [vp, i64, dp, dp, dp, C.c_double, C.c_double,
+                                               C.c_double, C.c_double, vp, vp,
+                                               C.POINTER(Options), vp]
+        L.rk_integrate_rkc_noalloc.restype = C.c_int
         L.rk_tape_bytes.argtypes = [vp, i64, i64, C.c_int32]
         L.rk_tape_bytes.restype = C.c_size_t
         L.rk_integrate_rkc_taped.argtypes = [vp, i64, dp, dp, dp, C.c_double, C.c_double,

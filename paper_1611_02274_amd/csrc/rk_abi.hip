@@ -75,14 +75,18 @@ struct rk_problem_s {
 
 namespace {
 
-// Device copy of the problem's uniform data on the current device.
-int problem_device_data(rk_problem p, const double** out) {
+// Device copy of the problem's uniform data on the current device, made on
+// first use unless may_alloc is false (then its absence is an error).
+int problem_device_data(rk_problem p, const double** out, bool may_alloc = true) {
   *out = nullptr;
   if (p->host_prm.empty()) return RK_OK;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
     return fail(RK_EHIP, "no usable current HIP device");
   std::lock_guard<std::mutex> lock(p->mu);
+  if (!p->dev_prm[dev] && !may_alloc)
+    return fail(RK_EINVAL, "the problem's constants are not on device %d yet (the first "
+                "allocating call with this problem on the device copies them there)", dev);
   if (!p->dev_prm[dev]) {
     void* d = nullptr;
     const size_t bytes = p->host_prm.size() * sizeof(double);
@@ -174,7 +178,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
               double t0, double t1, double rtol, double atol, int32_t* status, int32_t* stats,
               void* ws, size_t ws_bytes, const rk_options* opt, void* stream,
               const rkmi::TapeArgs* tape = nullptr, double* carry = nullptr,
-              bool want_carry = false) {
+              bool want_carry = false, bool static_ws = false) {
   g_err.clear();
   if (!p) return fail(RK_EINVAL, "problem handle is NULL");
   if (tape && !p->taped)
@@ -206,7 +210,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if ((rc = check_device_ptr(g, 8, "g", p->n_param == 0))) return rc;
   if ((rc = check_device_ptr(status, 4, "status", true))) return rc;
   if ((rc = check_device_ptr(stats, 4, "stats", true))) return rc;
-  if ((rc = check_device_ptr(ws, 8, "ws", true))) return rc;
+  if (!static_ws && (rc = check_device_ptr(ws, 8, "ws", true))) return rc;
   if (want_carry && (rc = check_device_ptr(carry, 8, "carry", false))) return rc;
   if (tape) {
     if ((rc = check_device_ptr(tape->tape, 256, "tape", false))) return rc;
@@ -228,7 +232,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   rkmi::LaunchArgs a;
   fill_args(a, method, n, y0, y1, g, t0, t1, rtol, atol, status, stats, ws, ws_bytes, opt);
   a.carry = carry;
-  if ((rc = problem_device_data(p, &a.prm))) return rc;
+  if ((rc = problem_device_data(p, &a.prm, !static_ws))) return rc;
   if (opt && opt->cost_order && tape) {
     // the pilot (one-lane plain kernel) and the sort work in the tape's own
     // order area; the taped kernel then takes the order map
@@ -466,6 +470,65 @@ int rk_integrate_rkc(rk_problem p, int64_t n_sys, const double* y0, double* y1, 
                      void* stream) {
   return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats, ws,
                    ws_bytes, opt, stream);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Workspace of the allocation-free RKC entry point: one array per device,
+// loaded with the code object and held until the process ends.  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[RK_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`.
+int scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(RK_EHIP, "no usable current HIP device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(RK_EHIP, "no device address for the scratch array on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rk_integrate_rkc_noalloc(rk_problem p, int64_t n_sys, const double* y0, double* y1,
+                             const double* g, double t0, double t1, double rtol, double atol,
+                             int32_t* status, int32_t* stats, const rk_options* opt,
+                             void* stream) {
+  g_err.clear();
+  if (!p) return fail(RK_EINVAL, "problem handle is NULL");
+  if (n_sys <= 0 || !(t1 > t0))   // nothing to size; integrate() checks and handles these
+    return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats,
+                     nullptr, 0, opt, stream, nullptr, nullptr, false, true);
+  const size_t need = rk_workspace_bytes(p, RK_METHOD_RKC, n_sys, opt);
+  if (!g_err.empty()) return RK_EHIP;
+  if (need > (size_t)RK_SCRATCH_BYTES)
+    return fail(RK_EWORKSPACE, "this call needs %zu bytes of workspace; the allocation-free "
+                "entry point has %zu (use rk_integrate_rkc with a workspace of that size)", need,
+                (size_t)RK_SCRATCH_BYTES);
+  void* ws = nullptr;
+  int rc;
+  if (need && (rc = scratch_address(&ws))) return rc;
+  return integrate(rkmi::kMethodRkc, p, n_sys, y0, y1, g, t0, t1, rtol, atol, status, stats, ws,
+                   need, opt, stream, nullptr, nullptr, false, true);
 }
 
 size_t rk_tape_bytes(rk_problem p, int64_t n_sys, int64_t max_accepted, int32_t ckpt_every) {
