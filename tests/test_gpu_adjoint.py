@@ -83,13 +83,12 @@ def _fd_system(orc, net, pb, gi, yi, wi, hs, ss, cols, e):
 def test_adjoint_full_size_vs_oracle_and_fd(rk, orc):
     """The 2^16-system 13-species adjoint workload (checkpoint every 16 accepted
     steps) at full size; on 256 spread systems the gradients equal the
-    oracle's adjoint and agree with central differences of the frozen step
-    sequence.  With h = 1e-6 the differences carry a rounding error of a few
-    1e-9 (eps |L| / h, grown over ~10^3 steps), so the 1e-6 relative bar is
-    taken over the 256 systems' gradients together (max norm, per kind: dL/dy0
-    and dL/dlnA); each system on its own agrees to 1e-4 with h = 1e-4, where
-    that rounding is 100 times smaller and the truncation error still far
-    below."""
+    oracle's adjoint, agree system by system to 1e-6 with complex-step
+    derivatives of the frozen step sequence (every component of dL/dy0 and
+    dL/dlnA; no cancellation, so each system is resolved on its own), and agree
+    with central differences (h = 1e-6) of that sequence.  The differences carry
+    a rounding error of a few 1e-9 (eps |L| / h, grown over ~10^3 steps), so
+    their 1e-6 bar is taken over the 256 systems together (max norm per kind)."""
     w_ = I.WORKLOADS["net13_adjoint"]
     say(f"case adjoint full-size n={w_.n}")
     net = I.network_of(w_.problem)
@@ -104,24 +103,30 @@ def test_adjoint_full_size_vs_oracle_and_fd(rk, orc):
     yo, d0, dt, so = orc.rkc_adjoint_batch(pb, ys, gs, ws, w_.t0, w_.t1, w_.rtol, w_.atol)
     assert _rel(dy0[:, idx], d0) <= 1e-9 and _rel(dth[:, idx], dt) <= 1e-9
     cols = np.arange(0, net.n_rx, 3)
+    n, nr = net.n_sp, net.n_rx
 
     def one(c):
         gi, yi, wi = gs[:, c], ys[:, c], ws[:, c]
         _, _, _, hs, ss = orc.rkc_solve(pb, gi, yi, w_.t0, w_.t1, w_.rtol, w_.atol)
-        return [_fd_system(orc, net, pb, gi, yi, wi, hs, ss, cols, e) for e in (1e-6, 1e-4)]
+        cy = np.array([orc.rkc_replay_jvp_cs(pb, gi, yi, w_.t0, hs, ss, wi, np.eye(n)[m])
+                       for m in range(n)])
+        ca = np.array([orc.rkc_replay_jvp_cs(pb, gi, yi, w_.t0, hs, ss, wi, np.zeros(n),
+                                             np.eye(nr)[j]) for j in range(nr)])
+        return cy, ca, _fd_system(orc, net, pb, gi, yi, wi, hs, ss, cols, 1e-6)
 
     with ThreadPoolExecutor(16) as ex:
-        fds = list(ex.map(one, range(len(idx))))
-    fy6 = np.stack([f[0][0] for f in fds], 1)
-    fa6 = np.stack([f[0][1] for f in fds], 1)
-    ay, aa = dy0[:, idx], dth[cols][:, idx]
-    rel_y, rel_a = _rel(ay, fy6), _rel(aa, fa6)
-    per_y = max(_rel(ay[:, c], f[1][0]) for c, f in enumerate(fds))
-    per_a = max(_rel(aa[:, c], f[1][1]) for c, f in enumerate(fds))
-    say("adjoint vs FD", dict(systems=len(idx), dy0_rel_h1e6=rel_y, dlnA_rel_h1e6=rel_a,
-                              dy0_rel_per_system_h1e4=per_y, dlnA_rel_per_system_h1e4=per_a))
+        res = list(ex.map(one, range(len(idx))))
+    ay, aa = dy0[:, idx], dth[:, idx]
+    per_y = max(_rel(ay[:, c], r[0]) for c, r in enumerate(res))
+    per_a = max(_rel(aa[:, c], r[1]) for c, r in enumerate(res))
+    fy6 = np.stack([r[2][0] for r in res], 1)
+    fa6 = np.stack([r[2][1] for r in res], 1)
+    rel_y, rel_a = _rel(ay, fy6), _rel(aa[cols], fa6)
+    say("adjoint vs complex step and FD",
+        dict(systems=len(idx), dy0_rel_worst_system_cs=per_y, dlnA_rel_worst_system_cs=per_a,
+             dy0_rel_fd_h1e6=rel_y, dlnA_rel_fd_h1e6=rel_a))
+    assert per_y <= 1e-6 and per_a <= 1e-6
     assert rel_y <= 1e-6 and rel_a <= 1e-6
-    assert per_y <= 1e-4 and per_a <= 1e-4
 
 
 def test_autograd_function(rk):
@@ -215,7 +220,8 @@ def test_rkck_adjoint_equals_oracle(rk, orc, problem, n, t1, K):
 def test_rkck_autograd_and_fd(rk, orc):
     """rkck_solve: loss.backward() gives the RKCK adjoint kernel's gradients;
     on a few systems they agree with central differences (h = 1e-6) of the
-    frozen RKCK step sequence, normwise to 1e-6."""
+    frozen RKCK step sequence, normwise to 1e-6, and on every system, component
+    by component, with complex-step derivatives of that sequence to 1e-6."""
     import torch
     say("case rkck autograd")
     net = I.network_of("net13")
@@ -250,6 +256,21 @@ def test_rkck_autograd_and_fd(rk, orc):
                        for j in cols])
         assert _rel(gy[:, i], fy) <= 1e-6
         assert _rel(ga[cols, i], fa) <= 1e-6
+
+    def cs(i):
+        gi, yi, wi = g[:, i], y0[:, i], w[:, i]
+        _, _, _, hs = orc.rkck_solve_rec(pb, gi, yi, 0.0, 5e-8, 1e-8, 1e-12)
+        cy = np.array([orc.rkck_replay_jvp_cs(pb, gi, yi, 0.0, hs, wi, np.eye(13)[m])
+                       for m in range(13)])
+        ca = np.array([orc.rkck_replay_jvp_cs(pb, gi, yi, 0.0, hs, wi, np.zeros(13),
+                                              np.eye(net.n_rx)[j]) for j in range(net.n_rx)])
+        return _rel(gy[:, i], cy), _rel(ga[:, i], ca)
+
+    with ThreadPoolExecutor(16) as ex:
+        worst = np.max(list(ex.map(cs, range(n))), axis=0)
+    say("rkck adjoint vs complex step", dict(systems=n, dy0_rel_worst_system=worst[0],
+                                             dlnA_rel_worst_system=worst[1]))
+    assert worst[0] <= 1e-6 and worst[1] <= 1e-6
 
 
 @pytest.mark.parametrize("method", ["rkc", "rkck"])
