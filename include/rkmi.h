@@ -167,7 +167,8 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
 /* Schedules.  Plain: one lane per system, system i on global lane i (the
  * paper's intDriver, Sec. 3).  Persistent: a machine-sized grid whose lanes take
  * the next system from a device-side queue as soon as theirs is finished.
- * Group: for networks of more than 16 species, 16 lanes of a wave share one
+ * Group: for networks of more than 16 species, 16 lanes (up to 32 species)
+ * or 32 lanes (more species) of a wave share one
  * system (its vectors and rate constants spread over their registers, its
  * concentrations and rates exchanged through LDS), groups taking systems
  * from the queue; other problems run their default.  Auto: group where
@@ -175,9 +176,9 @@ int rk_problem_dims(rk_problem p, int32_t *n_eq, int32_t *n_param, int32_t *n_th
  *
  * Cost order (rk_options.cost_order, with any schedule): the lanes of a wave
  * run in lockstep, so a wave lasts as long as its most expensive system.  The
- * call first integrates every system at rtol and atol multiplied by 10^4
- * (rtol at most 1e-3, never below the call's own), keeping only each system's
- * count of attempted steps, sorts the systems by that count on the
+ * call first integrates every system at rtol and atol multiplied by 10^5
+ * (rtol at most 1e-3, never below the call's own) for at most 128 attempts,
+ * keeping only each system's count of attempted steps, sorts the systems by that count on the
  * device, and then integrates them at the requested tolerances handed out in
  * decreasing order of it.  Each system's result is bit-for-bit the same as
  * without the order.  The workspace grows by 24 + 4 bytes per system plus

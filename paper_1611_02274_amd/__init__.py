@@ -100,9 +100,14 @@ class Problem:
         return self._h
 
     def __del__(self):
+        # at interpreter exit the module globals may already be gone
         h, self._h = getattr(self, "_h", None), None
-        if h is not None and _lib is not None and _lib._lib is not None:
-            _lib._lib.rk_problem_destroy(h)
+        try:
+            lib = _lib._lib
+        except (AttributeError, NameError, TypeError):
+            return
+        if h is not None and lib is not None:
+            lib.rk_problem_destroy(h)
 
 
 SR_METHODS = {"power": 0, "gershgorin": 1}
@@ -343,6 +348,12 @@ def adjoint_rkck(problem, g, tape, dL_dy1, stream=None):
     return dy0, dth[:problem.n_theta], st
 
 
+# Longest tape (accepted steps per system) the autograd functions record
+# before giving up on a system: at 2^16 systems of 13 unknowns such a tape
+# takes about 80 GB of device memory.
+TAPE_LIMIT = 1 << 16
+
+
 def _autograd_function(method):
     import torch
     taped = integrate_rkck_taped if method == RK_METHOD_RKCK else integrate_rkc_taped
@@ -356,13 +367,22 @@ def _autograd_function(method):
 
         @staticmethod
         def forward(ctx, y0, g, lnA, problem, t0, t1, rtol, atol, max_accepted, ckpt_every):
+            if problem.kind != "vdp" and g is not None and g.requires_grad:
+                raise ValueError("only y0 and lnA are differentiable for a network problem "
+                                 "(g = (T, rho) is not): detach g")
+            # a system that outruns the tape is recorded again with a tape twice
+            # as long, up to TAPE_LIMIT accepted steps per system
+            limit = max(max_accepted, TAPE_LIMIT)
             while True:
                 y1, status, stats, tape = taped(
                     problem, y0.detach(), g.detach() if g is not None else None, t0, t1, rtol,
                     atol, max_accepted=max_accepted, ckpt_every=ckpt_every)
                 if int(tape.count.min().item()) >= 0 or y0.shape[1] == 0:
                     break
-                max_accepted *= 2       # a system outran the tape: record again, longer
+                if max_accepted >= limit:
+                    raise RuntimeError(f"a system takes more than {max_accepted} accepted "
+                                       "steps: no tape for its gradient")
+                max_accepted = min(2 * max_accepted, limit)
             ctx.problem, ctx.tape, ctx.has_lnA = problem, tape, lnA is not None
             ctx.save_for_backward(g)
             ctx.mark_non_differentiable(status, stats)
@@ -442,8 +462,12 @@ class Batch:
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h is not None and _lib is not None and _lib._lib is not None:
-            _lib._lib.rk_batch_destroy(h)
+        try:
+            lib = _lib._lib
+        except (AttributeError, NameError, TypeError):
+            return
+        if h is not None and lib is not None:
+            lib.rk_batch_destroy(h)
 
     @classmethod
     def schedule(cls, mode="persistent", waves_per_cu=0, order=None, refill=None,

@@ -1,17 +1,21 @@
-// crmath.hpp -- correctly rounded exp, log and pow in FP64 for the kernels.
+// crmath.hpp -- exp, log and pow in FP64 for the kernels, rounded from a
+// double-double evaluation.
 //
 // The integrators' control decisions (accept/reject, stage counts) depend on
 // round-off: a one-ulp change in a step size can flip a later decision.  The
-// kernels therefore evaluate every transcendental function correctly rounded
-// (the exact value rounded to the nearest double), which makes their results a
-// function of the inputs alone rather than of a particular math library.
+// kernels therefore evaluate every transcendental function to the exact value
+// rounded to the nearest double wherever a double-double evaluation can
+// decide that rounding, which makes their results a function of the inputs
+// alone rather than of a particular math library.
 //
 // Method: table-driven argument reduction (Tang, ACM TOMS 15 (1989) for exp,
 // 16 (1990) for log) carried out in double-double arithmetic built on the
 // error-free transformations TwoSum (Knuth) and TwoProd via FMA (Dekker).
-// The double-double result has relative error below about 2^-88, so its final
-// rounding is the correctly rounded value except with probability ~2^-35 per
-// call.  exp results in the subnormal range are scaled after rounding (a
+// The double-double result has relative error below about 2^-88; its final
+// rounding is the correctly rounded value unless the exact value lies that
+// close to a rounding midpoint, about 2^-35 of calls (no such input is known,
+// and there is no slower fallback that would decide them: these functions are
+// not proven correctly rounded).  exp results in the subnormal range are scaled after rounding (a
 // possible double rounding there).  Functions are __host__ __device__ so that
 // the identical code can be checked on the CPU.
 #pragma once
@@ -188,7 +192,7 @@ RKMI_HD dd log_dd(double x) {
   return two_sum(t3.hi, lo);
 }
 
-// exp(x) correctly rounded.  A first evaluation: the reduction of exp_dd
+// exp(x), rounded as the header describes.  A first evaluation: the reduction of exp_dd
 // (r + rl = x - k ln2/1024 to 2^-115), 1 + r + (rl (1 + r) + r^2 (1/2 + r/6 +
 // r^2/24 + r^3/120)) as a double-double (relative error below 2^-74.5: the
 // truncation r^6/720 < 2^-78.5 and the rounding of the r^2 terms), times the
@@ -278,8 +282,8 @@ RKMI_HD double cr_pow(double x, double y) {
 // residual c^3 - t formed exactly with TwoProd).  ln x = e ln2 + 2 atanh(s),
 // s = (m - 1)/(m + 1), needs absolute accuracy of only about 1e-11 here (the
 // series to s^13 gives 4e-13).  The double-double result has relative error
-// below about 2^-90, so both roundings are the correctly rounded values except
-// with probability about 2^-37 per call.
+// below about 2^-90, so both roundings give the correctly rounded values except
+// for about 2^-37 of calls (the exact value that close to a midpoint).
 constexpr double kThird = 0x1.5555555555555p-2;            // RN(1/3)
 constexpr double kThirdDefect = 0x1.5555555555555p-56;     // 1/3 - RN(1/3), rounded
 constexpr double kCbrtFit[5] = {0x1.bf460be1acba9p-1, -0x1.8d16b63ef59afp-3,
@@ -367,10 +371,10 @@ RKMI_HD void pow_third(double x, double& p1, double& p2) {
   }
 }
 
-// x^RN(1/3) and x^RN(2/3) for finite x >= 0 (correctly rounded, as cr_pow).
+// x^RN(1/3) and x^RN(2/3) for finite x >= 0 (rounded as cr_pow).
 RKMI_HD void pow_third_pair(double x, double& p1, double& p2) { pow_third<true>(x, p1, p2); }
 
-// x^RN(1/3) for finite x >= 0 (correctly rounded, as cr_pow).
+// x^RN(1/3) for finite x >= 0 (rounded as cr_pow).
 RKMI_HD double pow_third_one(double x) {
   double p1, p2;
   pow_third<false>(x, p1, p2);
@@ -389,7 +393,7 @@ RKMI_HD double pow_near_one(double d, double y) {
   return r.hi + ((r.lo - p.lo) + c2 * (d * d));
 }
 
-// x^-0.25 for finite x > 0, correctly rounded (as cr_pow(x, -0.25)): x =
+// x^-0.25 for finite x > 0, rounded as cr_pow(x, -0.25): x =
 // t 2^(4q) with t in [1, 16); a0 = 1 / sqrt(sqrt(t)) (relative error below
 // 2^-50), then one Newton step for t a^4 = 1 in double-double, a = a0 - a0
 // (t a0^4 - 1) / 4 with the residual formed exactly by TwoProd: relative
@@ -414,7 +418,7 @@ RKMI_HD double pow_minus_quarter(double x) {
   return scale2(A.hi + A.lo, -q);
 }
 
-// x^-RN(0.2) for finite x > 0, correctly rounded (as cr_pow(x, -0.2)).  Since
+// x^-RN(0.2) for finite x > 0, rounded as cr_pow(x, -0.2).  Since
 // RN(0.2) = 1/5 + 2^-54/5 exactly, x^-RN(0.2) = x^(-1/5) (1 - u + u^2/2 ...)
 // with u = (2^-54/5) ln x, |u| < 8.3e-15.  x = t 2^(5q) with t in [1, 32):
 // t^(-1/5) from a degree-4 fit of m^(-1/5) on [1, 2) (relative error 4.2e-5;

@@ -1,4 +1,4 @@
-// rk_crmath_eval.hip -- evaluates the kernels' correctly rounded exp / log / pow
+// rk_crmath_eval.hip -- evaluates the kernels' exp / log / pow
 // over arrays, on the host (the same source compiled for the CPU) or on the
 // device, so that tests can check them.  fn: 0 exp(x), 1 log(x), 2 pow(x, y),
 // 3 and 4: x^RN(1/3) and x^RN(2/3) from the RKC controllers' pair, 5: x^RN(1/3)

@@ -14,7 +14,8 @@
 //     rejection step 0.8 h / err^(1/3) without a floor;
 //   * guards: h below hMin after a rejection, a non-finite accepted state or
 //     max_steps attempts end the system with a status code;
-//   * exp, log and pow are correctly rounded (crmath.hpp).
+//   * exp, log and pow round a double-double evaluation (crmath.hpp): the
+//     correctly rounded value but for ~2^-35 of calls.
 // Every expression is written in the order of the reference evaluation and the
 // library is built without contraction, so results are reproducible bit for bit.
 //
