@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librkmi.so")
+# RKMI_LIBRARY names another build of the library (a profiling variant)
+LIB_PATH = os.environ.get("RKMI_LIBRARY") or os.path.join(HERE, "librkmi.so")
 
 RK_OK, RK_EINVAL, RK_ENOMEM, RK_EHIP, RK_EUNSUPPORTED, RK_EWORKSPACE = 0, -1, -2, -3, -4, -5
 RK_SYS_OK, RK_SYS_NONFINITE, RK_SYS_HMIN, RK_SYS_MAXSTEPS, RK_SYS_TAPE = 0, 1, 2, 3, 4
@@ -122,6 +123,11 @@ def lib():
                                              C.POINTER(Options), C.POINTER(BatchSchedule),
                                              vp, C.c_size_t, vp]
         L.rk_batch_integrate_rkc.restype = C.c_int
+        # internal: FP64 vector-ALU throughput probe (benchmark ceilings)
+        L.rkmi_peak_threads.argtypes = []
+        L.rkmi_peak_threads.restype = i64
+        L.rkmi_peak_fp64.argtypes = [C.c_int, i64, dp, C.POINTER(C.c_double), vp]
+        L.rkmi_peak_fp64.restype = C.c_int
         _lib = L
     return _lib
 

@@ -376,49 +376,121 @@ def _table(name, ctype, values, per_line=16):
     return f"  static constexpr {ctype} {name}[{len(values)}] = {{\n      {body}}};"
 
 
+# Group variants: a lane's species list is consumed in chunks of this many
+# terms; its first species' list is padded to a whole number of chunks.
+GROUP_TERM_CHUNK = 4
+
+
+def _group_positions(net, L, R):
+    """Reaction -> rate position p = m * L + r (slot m of lane r).  Reactions
+    with a one-species side (times [M]) fill the last slots, so the kernel
+    selects [M] for an operand only there; the others fill the first slots in
+    reaction order.  Returns (position of each reaction, reaction of each
+    position or -1, first slot that may hold a [M] reaction)."""
+    nr, n = net.n_rx, net.n_sp
+    third = [j for j in range(nr) if int(net.reac[j][1]) < 0 or int(net.prod[j][1]) < 0]
+    plain = [j for j in range(nr) if j not in set(third)]
+    m_slots = -(-len(third) // L) if third else 0
+    # the [M] slots also take the plain reactions that do not fit before them
+    m_first = R - m_slots
+    while m_first > 0 and len(plain) > m_first * L:
+        m_first -= 1
+    front = plain[:m_first * L]
+    back = plain[m_first * L:] + third
+    assert len(back) <= (R - m_first) * L
+    pos_of = [-1] * nr
+    rx_of = [-1] * (R * L)
+    for p, j in enumerate(front):
+        pos_of[j], rx_of[p] = p, j
+    for t, j in enumerate(back):
+        p = m_first * L + t
+        pos_of[j], rx_of[p] = p, j
+    return pos_of, rx_of, (m_first if third else R)
+
+
+def _group_species(lens, L, chunk):
+    """Species -> (lane, slot) for two slots per lane: each lane sums its
+    slot-0 species' terms (padded to whole chunks), then its slot-1 species'.
+    The heaviest lists go alone to a lane (in slot 1: no padding); the rest
+    are paired heavy with light, each pair ordered for the shorter padded
+    sequence.  Returns sp[slot * L + lane] (-1: none)."""
+    n = len(lens)
+    assert L < n <= 2 * L
+    order = sorted(range(n), key=lambda k: (-lens[k], k))
+    single = 2 * L - n
+    sp = [-1] * (2 * L)
+    for r in range(single):
+        sp[L + r] = order[r]
+    rest = order[single:]
+    m = len(rest)
+
+    def padded(k):
+        return -(-lens[k] // chunk) * chunk
+
+    for i in range(m // 2):
+        a, b = rest[i], rest[m - 1 - i]
+        if padded(b) + lens[a] < padded(a) + lens[b]:
+            a, b = b, a
+        sp[single + i] = a
+        sp[L + single + i] = b
+    return sp
+
+
 def group_source(net, tag: str, lanes: int | None = None) -> str:
-    """The group variant of a network: lane r of a group of `lanes` owns
-    reactions m*lanes + r and the species of its slots m; species go to slots
-    in order of their term counts so a slot's lists have similar lengths.
-    Per lane: the species of each slot, the packed species indices of each
-    owned reaction, the signed rate indices of each owned species' sum (packed
-    into registers), for the kernels of rk_group.hpp."""
+    """The group variant of a network (kernels of rk_group.hpp): lane r of a
+    group of `lanes` computes the rates of progress at its positions
+    p = m*lanes + r (_group_positions) and owns the species of its two slots
+    (_group_species); per lane: the species of each slot, the packed operand
+    species of each position's reaction, and the signed rate positions of its
+    species' sums in reaction order (slot 0's list, padded to whole chunks,
+    then slot 1's), packed into registers."""
     n, nr = net.n_sp, net.n_rx
     L = lanes or group_lanes(n)
     S, R = -(-n // L), -(-nr // L)
+    assert S == 2, "group variants hold two species per lane"
     assert n < 255, "species indices are packed in bytes"
+    chunk = GROUP_TERM_CHUNK
+    pos_of, rx_of, m_first = _group_positions(net, L, R)
     rx = []
-    for m in range(R):
-        for r in range(L):
-            j = m * L + r
-            if j < nr:
-                a, b = int(net.reac[j][0]), int(net.reac[j][1])
-                c, d = int(net.prod[j][0]), int(net.prod[j][1])
-                b = n if b < 0 else b
-                d = n if d < 0 else d
-                rx.append(a | b << 8 | c << 16 | d << 24)
-            else:
-                rx.append(0)
-    # term codes index the signed-rate area QQ = [q_0..q_{NR-1}, 0, -q_0..-q_{NR-1}]:
-    # +q_j at j, -q_j at NR + 1 + j, the zero at NR pads short lists
-    terms = [[(c >> 1) + (nr + 1) * (c & 1) for c in lst] for lst in _species_terms(net)]
-    order = sorted(range(n), key=lambda k: (-len(terms[k]), k))
-    sp = [order[i] if i < n else -1 for i in range(S * L)]
-    sentinel = nr
-    bits = (2 * nr + 1).bit_length()
+    for p in range(R * L):
+        j = rx_of[p]
+        if j >= 0:
+            a, b = int(net.reac[j][0]), int(net.reac[j][1])
+            c, d = int(net.prod[j][0]), int(net.prod[j][1])
+            b = n if b < 0 else b
+            d = n if d < 0 else d
+            rx.append(a | b << 8 | c << 16 | d << 24)
+        else:
+            rx.append(0)
+    # LDS area of a system (doubles): C [0, N] | rates +q at kOffQ + p, p < R*L,
+    # the zero at kOffQ + R*L, norm scratch (N, 16-byte aligned) | -q at
+    # kOffQ + kNegOff + p
+    off_q = n + 1 + (n + 1) % 2
+    off_red = off_q + R * L + 1 + (off_q + R * L + 1) % 2
+    neg = off_red - off_q + n
+    lds_per_system = off_q + neg + R * L
+    lds_per_system += lds_per_system % 2
+    sentinel = R * L
+    terms = [[pos_of[c >> 1] + neg * (c & 1) for c in lst] for lst in _species_terms(net)]
+    lens = [len(t) for t in terms]
+    sp = _group_species(lens, L, chunk)
+    seqs, bnd = [], []
+    for r in range(L):
+        k0, k1 = sp[r], sp[L + r]
+        l0 = terms[k0] if k0 >= 0 else []
+        l0 = l0 + [sentinel] * ((-len(l0)) % chunk)
+        l1 = terms[k1] if k1 >= 0 else []
+        seqs.append(l0 + l1)
+        bnd.append(len(l0) // chunk)
+    tot = max(len(q) for q in seqs)
+    tot += (-tot) % chunk
+    seqs = [q + [sentinel] * (tot - len(q)) for q in seqs]
+    bits = (neg + R * L).bit_length()
     per_word = 32 // bits
-    off = [0]
-    for m in range(S):
-        off.append(off[-1] + max(len(terms[k]) if k >= 0 else 0 for k in sp[m * L:(m + 1) * L]))
-    n_words = max(1, -(-off[-1] // per_word))
+    n_words = max(1, -(-tot // per_word))
     tc = [0] * (n_words * L)
     for r in range(L):
-        seq = []
-        for m in range(S):
-            k = sp[m * L + r]
-            lst = terms[k] if k >= 0 else []
-            seq += [lst[t] if t < len(lst) else sentinel for t in range(off[m + 1] - off[m])]
-        for t, code in enumerate(seq):
+        for t, code in enumerate(seqs[r]):
             tc[(t // per_word) * L + r] |= code << ((t % per_word) * bits)
     return f"""
 // Group variant: {L} lanes per system (rk_group.hpp).
@@ -429,47 +501,61 @@ struct GNet {{
   static constexpr int kGroupLanes = {L};
   static constexpr bool kColumns = false;
   static constexpr int kLaneDoubles = 0;
-  // RKC's controller state pushes the group kernel past 256 registers (one
-  // wave per SIMD); two waves, with spills outside the stage loops, run faster
+  // three waves per SIMD: the evaluation loop fits 168 registers (the power
+  // method and the set-up of a system run out of line)
   static constexpr int kWavesPerEuRkc = 2;
+  static constexpr int kWavesPerEuRkck = 3;
   static constexpr int S = {S};
   static constexpr int R = {R};
+  static constexpr int kMSlot = {m_first};   // first slot that may hold a [M] reaction
   static constexpr int kOffC = 0;
-  static constexpr int kOffQ = N + 1;
-  static constexpr int kOffRed = kOffQ + 2 * NR + 1;
-  static constexpr int kLdsPerSystem = kOffRed + N;
+  static constexpr int kOffQ = {off_q};
+  static constexpr int kSentinel = {sentinel};
+  static constexpr int kNegOff = {neg};
+  static constexpr int kOffRed = {off_red};
+  static constexpr int kLdsPerSystem = {lds_per_system};
   static constexpr int kTermBits = {bits};
   static constexpr int kTermsPerWord = {per_word};
   static constexpr int kTermWords = {n_words};
+  static constexpr int kTermLen = {tot};
+  static constexpr int kChunk = {chunk};
   using Params = const double*;
 {_table("kSp", "int", sp)}
+{_table("kRxOf", "int16_t", rx_of)}
 {_table("kRx", "uint32_t", rx)}
-{_table("kTermOff", "int", off)}
 {_table("kTc", "uint32_t", tc)}
+{_table("kBnd", "int", bnd)}
   struct Lane {{
     double kf[R], kr[R];
     uint32_t rx[R];
     uint32_t tc[kTermWords];
     double W[S], iW[S];
     double rho, irho;
+    int bnd;   // chunks of the slot-0 list
   }};
+  // The forward rate constants of a lane's positions into the group's rate
+  // area; once per system, out of line (the exponentials' temporaries do not
+  // count against the registers of the evaluation loop).
+  __device__ __attribute__((noinline)) static void rates(Params p, double T, double* lds, int r) {{
+    const double lnT = crm::cr_log(T);
+    double* const Q = lds + kOffQ;
+#pragma nounroll
+    for (int m = 0; m < R; ++m) {{
+      const int j = kRxOf[m * kL + r];
+      if (j >= 0) Q[m * kL + r] = crm::cr_exp(p[j] + p[NR + j] * lnT - p[2 * NR + j] / T);
+    }}
+  }}
   __device__ static void init(Lane& L, const Params& p, const double* __restrict__ g, int64_t i,
                               int64_t n, const Grp<GNet>& x) {{
     const double T = g[i];
     const double rho = g[n + i];
-    const double lnT = crm::cr_log(T);
     double* const Q = x.lds + kOffQ;
-    // rate constants through the group's rate area (one copy of the exponential)
-#pragma nounroll
-    for (int m = 0; m < R; ++m) {{
-      const int j = m * kL + x.r;
-      if (j < NR) Q[j] = crm::cr_exp(p[j] + p[NR + j] * lnT - p[2 * NR + j] / T);
-    }}
+    rates(p, T, x.lds, x.r);
 #pragma unroll
     for (int m = 0; m < R; ++m) {{
-      const int j = m * kL + x.r;
-      L.kf[m] = j < NR ? Q[j] : 0.0;
-      L.kr[m] = j < NR ? L.kf[m] * p[3 * NR + j] : 0.0;
+      const int j = kRxOf[m * kL + x.r];
+      L.kf[m] = j >= 0 ? Q[m * kL + x.r] : 0.0;
+      L.kr[m] = j >= 0 ? L.kf[m] * p[3 * NR + j] : 0.0;
       L.rx[m] = kRx[m * kL + x.r];
     }}
 #pragma unroll
@@ -482,7 +568,8 @@ struct GNet {{
     }}
     L.rho = rho;
     L.irho = 1.0 / rho;
-    if (x.r == 0) Q[NR] = 0.0;
+    L.bnd = kBnd[x.r];
+    if (x.r == 0) Q[kSentinel] = 0.0;
   }}
 }};
 """

@@ -102,22 +102,35 @@ struct TapeRec {
   }
 };
 
-// Stage records of one step in the lane's columns: record j (1..s) holds
-// w_{j-1} and (mu_j, nu_j, mut_j, gt_j); record 1 holds w_0 and mut_1.
+// Stage records held in LDS (the rest in the lane's workspace columns): the
+// reverse sweep writes and reads a step's records once each, and steps of up
+// to this many stages (nearly all) keep them on chip.
+constexpr int kAdjLdsStages = 2;
+
+// Stage records of one step: record j (1..s) holds w_{j-1} and (mu_j, nu_j,
+// mut_j, gt_j); record 1 holds w_0 and mut_1.  Records 1..kAdjLdsStages are
+// in the lane's LDS column (lcol), the others in its workspace column (col);
+// both with stride kLdsStride.
 template <int N>
 struct StageRecorder {
   static constexpr bool kStopAtLast = true;
   static constexpr int kRows = N + 4;
+  double* lcol;
   double* col;
+  RKMI_HD double* rec(int j) const {
+    return j <= kAdjLdsStages ? lcol + (int64_t)(j - 1) * kRows * kLdsStride
+                              : col + (int64_t)(j - 1) * kRows * kLdsStride;
+  }
   template <class V>
   RKMI_HD void first(const V& w0, double mut1) {
+    double* const r = rec(1);
 #pragma unroll
-    for (int k = 0; k < N; ++k) col[k * kLdsStride] = w0[k];
-    col[N * kLdsStride] = mut1;
+    for (int k = 0; k < N; ++k) r[k * kLdsStride] = w0[k];
+    r[N * kLdsStride] = mut1;
   }
   template <class V>
   RKMI_HD void stage(int j, const V& w, double mu, double nu, double mut, double gt) {
-    double* r = col + (int64_t)(j - 1) * kRows * kLdsStride;
+    double* r = rec(j);
 #pragma unroll
     for (int k = 0; k < N; ++k) r[k * kLdsStride] = w[k];
     r[N * kLdsStride] = mu;
@@ -172,7 +185,7 @@ template <class Prob>
 RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int64_t i,
                                const double* g, const TapeView& T, int max_stages,
                                const double* w, double* dy0, double* dth, double* slot,
-                               double* col) {
+                               double* col, double* lcol) {
   constexpr int N = Prob::N, NT = Prob::kNTheta;
   using V = RegVec<N>;
   typename Prob::Lane L;
@@ -186,6 +199,7 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
   for (int q = 0; q < NT; ++q) th[q] = 0.0;
   int32_t st = M < 0 ? kSysTape : kSysOk;
   double* const ys = col + (int64_t)max_stages * StageRecorder<N>::kRows * kLdsStride;
+  StageRecorder<N> Rec{lcol, col};
   for (int64_t seg = M > 0 ? (M - 1) / T.K : -1; st == kSysOk && seg >= 0; --seg) {
     const int64_t k0 = seg * T.K;
     const int64_t k1 = (k0 + T.K < M) ? k0 + T.K : M;
@@ -217,8 +231,7 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
       {
         V F, wlast;
         Prob::rhs(L, prm, y, F);
-        StageRecorder<N> R{col};
-        rkc_step<Prob, StageRecorder<N>>(L, prm, y, F, hk, sk, wlast, slot, &R);
+        rkc_step<Prob, StageRecorder<N>>(L, prm, y, F, hk, sk, wlast, slot, &Rec);
       }
       V cur, m1, m2, A0, f0b, u, jtu, Wv;
 #pragma unroll
@@ -230,7 +243,7 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
         f0b[r] = 0.0;
       }
       for (int j = sk; j >= 2; --j) {
-        const double* const rj = col + (int64_t)(j - 1) * StageRecorder<N>::kRows * kLdsStride;
+        const double* const rj = Rec.rec(j);
 #pragma unroll
         for (int r = 0; r < N; ++r) Wv[r] = rj[r * kLdsStride];
         const double mu = rj[N * kLdsStride], nu = rj[(N + 1) * kLdsStride];
@@ -265,9 +278,10 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
           m2[r] = 0.0;
         }
       }
+      const double* const r1 = Rec.rec(1);
 #pragma unroll
-      for (int r = 0; r < N; ++r) Wv[r] = col[r * kLdsStride];
-      const double mh1 = col[N * kLdsStride] * hk;
+      for (int r = 0; r < N; ++r) Wv[r] = r1[r * kLdsStride];
+      const double mh1 = r1[N * kLdsStride] * hk;
 #pragma unroll
       for (int r = 0; r < N; ++r) {
         A0[r] += cur[r];
@@ -390,6 +404,14 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEu<Prob>::value))) void taped_kernel(
   taped_system<Prob, Method>(prm, n, i, y0, y1, g, c, status, stats, T, lds + threadIdx.x);
 }
 
+// LDS doubles per lane of the reverse kernel: the problem's slot, then (RKC)
+// the on-chip stage records.
+template <class Prob, int Method>
+constexpr int adjoint_lds_doubles() {
+  return kernel_lds_doubles<Prob, Method>() +
+         (Method == kMethodRkc ? kAdjLdsStages * StageRecorder<Prob::N>::kRows : 0);
+}
+
 template <class Prob, int Method>
 __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Params prm, int64_t n,
                                                              const double* __restrict__ g,
@@ -400,7 +422,7 @@ __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Para
                                                              int32_t* __restrict__ status,
                                                              double* cols,
                                                              const int32_t* __restrict__ order) {
-  __shared__ double lds[kernel_lds_doubles<Prob, Method>() * kLdsStride];
+  __shared__ double lds[adjoint_lds_doubles<Prob, Method>() * kLdsStride];
   const int64_t q = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (q >= n) return;
   const int64_t i = order ? (int64_t)order[q] : q;   // lane q sweeps system order[q]
@@ -411,7 +433,8 @@ __global__ __launch_bounds__(kLdsStride) void adjoint_kernel(typename Prob::Para
   if constexpr (Method == kMethodRkck)
     st = adjoint_system_rkck<Prob>(prm, n, i, g, T, w, dy0, dth, lds + threadIdx.x, col);
   else
-    st = adjoint_system<Prob>(prm, n, i, g, T, max_stages, w, dy0, dth, lds + threadIdx.x, col);
+    st = adjoint_system<Prob>(prm, n, i, g, T, max_stages, w, dy0, dth, lds + threadIdx.x, col,
+                              lds + kernel_lds_doubles<Prob, Method>() * kLdsStride + threadIdx.x);
   if (status) status[i] = st;
 }
 
@@ -524,12 +547,13 @@ int host_adjoint(const AdjointArgs* a) {
   const int64_t rows = ck ? adjoint_rows<Prob, kMethodRkck>(0, a->tape.K)
                           : adjoint_rows<Prob, kMethodRkc>(a->max_stages, a->tape.K);
   std::vector<double> col((size_t)rows * kLdsStride);
+  std::vector<double> lcol((size_t)kAdjLdsStages * StageRecorder<Prob::N>::kRows * kLdsStride);
   for (int64_t i = 0; i < a->n; ++i) {
     const int32_t st =
         ck ? adjoint_system_rkck<Prob>(a->prm, a->n, i, a->g, T, a->w, a->dy0, a->dth,
                                        slot.data(), col.data())
            : adjoint_system<Prob>(a->prm, a->n, i, a->g, T, a->max_stages, a->w, a->dy0,
-                                  a->dth, slot.data(), col.data());
+                                  a->dth, slot.data(), col.data(), lcol.data());
     if (a->status) a->status[i] = st;
   }
   return kLaunchOk;

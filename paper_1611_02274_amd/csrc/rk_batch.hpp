@@ -119,7 +119,7 @@ constexpr int kRaggedWavesPerEu = 2;
 template <class... P>
 __global__ __launch_bounds__(kLdsStride)
 __attribute__((amdgpu_waves_per_eu(kRaggedWavesPerEu))) void ragged_kernel(BatchParams bp, Ctl c) {
-  __shared__ double lds[batch_lds_doubles<P...>()];
+  __shared__ __attribute__((aligned(16))) double lds[batch_lds_doubles<P...>()];
   double* const colbase = bp.cols ? bp.cols + (int64_t)blockIdx.x * bp.col_block : nullptr;
   for (int r = 0; r < bp.n_net; ++r) {
     const int k = bp.order[r];
@@ -148,7 +148,7 @@ template <class... P>
 __global__ __launch_bounds__(kLdsStride) void interleaved_kernel(BatchParams bp, Ctl c,
                                                                  const int32_t* __restrict__ map,
                                                                  int64_t n_total) {
-  __shared__ double lds[batch_lds_doubles<P...>()];
+  __shared__ __attribute__((aligned(16))) double lds[batch_lds_doubles<P...>()];
   const int64_t i = (int64_t)blockIdx.x * kLdsStride + threadIdx.x;
   if (i >= n_total) return;
   const int32_t code = map[i];

@@ -2,27 +2,32 @@
 //
 // For networks whose vectors do not fit one lane's registers, a group of L
 // consecutive lanes integrates one system: lane r of the group owns the
-// unknowns k = m L + r (m < S) of every vector and the reactions
-// j = m L + r (m < R) with their rate constants, all in registers.  The
-// right-hand side exchanges concentrations and rates of progress through the
-// group's LDS area:
-//   1. owners write C_k = (rho Y_k) / W_k; lane 0 forms [M] = sum_k C_k;
-//   2. owners of reaction j write q_j = k_f prod_R C - k_r prod_P C and -q_j;
-//   3. owners of species k sum their signed q_j in reaction order, then
+// unknowns of its slots and the rates of progress at positions p = m L + r
+// (m < R), with their rate constants, all in registers.  The right-hand side
+// exchanges concentrations and rates of progress through the group's LDS
+// area:
+//   1. owners write C_k = (rho Y_k) / W_k; [M] = sum_k C_k in species order is
+//      passed along a chain of lanes (group_chain_sum) while the rates of the
+//      reactions without [M] are formed;
+//   2. the lane of position p writes q and -q of its reaction;
+//   3. each lane sums the signed rates of its species in reaction order, then
 //      f_k = (W_k omega_k) / rho,
 // which is the per-system evaluation order, so results equal the one-lane
-// kernels and the oracle bit for bit.  Weighted norms are formed in species
-// order from the group's LDS scratch by every lane, so the step-size
-// controller runs identically (and redundantly) in the L lanes.  The groups
-// of a wave hold different systems and may diverge like lanes do.
+// kernels and the oracle bit for bit.  Weighted norms (sums in species order)
+// take the same chain, so the step-size controller runs identically (and
+// redundantly) in the L lanes.  The groups of a wave hold different systems
+// and may diverge like lanes do.
 //
-// A group problem GP supplies N, NR, kL (lanes per system), S, R, the LDS
-// layout (kOffC, kOffQ, kOffRed, kLdsPerSystem), the tables kRx (packed
-// species indices of each reaction, [M] as index N), kTermOff / kTerms
-// (signed rate indices of each species' sum in reaction order), Params,
-// Lane, init(Lane&, prm, g, i, n, x); species of slot m of
-// lane r: kSp[m L + r] (-1 for none), chosen so each slot's term lists have
-// similar lengths; each lane's term codes are packed in its registers.
+// A group problem GP supplies N, NR, kL (lanes per system), S (= 2 slots), R,
+// kMSlot (the first slot whose reactions may have a one-species side times
+// [M]), the LDS layout (kOffC, kOffQ, kSentinel, kNegOff, kOffRed,
+// kLdsPerSystem: +q at kOffQ + p, the zero at kOffQ + kSentinel, -q at
+// kOffQ + kNegOff + p), the tables kSp (species of slot m of lane r at
+// m L + r, -1 for none), kRx (packed operand species of each position's
+// reaction, [M] as index N), kTc (each lane's signed rate positions, packed:
+// its slot-0 species' list padded with the zero to whole chunks of kChunk
+// terms, then its slot-1 species' list, kTermLen in all) and kBnd (the chunks
+// of the slot-0 list), Params, Lane, init(Lane&, prm, g, i, n, x).
 #pragma once
 
 #include "rk_device.hpp"
@@ -53,14 +58,60 @@ __device__ inline void group_sync() { __syncthreads(); }
 // from a lane's constant tables are recomputed in each evaluation instead of
 // being hoisted out of the integration loop into ~100 extra live registers.
 __device__ inline void opaque(uint32_t& v) { asm volatile("" : "+v"(v)); }
+// The same for a double: the value is formed here, not later.
+__device__ inline void opaque_f64(double& v) { asm volatile("" : "+v"(v)); }
 
 template <class GP>
 __device__ inline bool owns(const Grp<GP>& x, int m) {
   return x.sp[m] >= 0;
 }
 
-// sum_k t_k over k = 0..N-1 in order, t_k held by the owners (slot m of lane
-// r holds k = m L + r); every lane of the group gets the same value.
+// v shifted one lane up within each row of 16 lanes (lane i gets lane i - 1's
+// value; the first lane of a row gets +0).
+__device__ inline double dpp_row_shr1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x111, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// ((0 + v_0) + v_1) + ... + v_{n-1}: the sum of n values of the group's LDS
+// area at v (16-byte aligned) in index order, returned to every lane of the
+// group.  Lane r of the group takes v_{8r} .. v_{8r+7}; the running sum passes
+// from lane to lane (lane r adds its values, in order, to the sum of the lanes
+// before it), so each addition is the one of the serial loop.  Adding +0 for
+// the slots past n changes nothing: a sum that starts at +0 is never -0.  The
+// chain stays within one row of 16 lanes (a group starts at a multiple of kL).
+template <class GP, int Nv>
+__device__ double group_chain_sum(const Grp<GP>& x, const double* v) {
+  constexpr int kPer = 8, kLanes = (Nv + kPer - 1) / kPer;
+  static_assert(kLanes <= GP::kL && kLanes <= 16, "chain within a row of the group");
+  const int r = x.r;
+  const double2* p = reinterpret_cast<const double2*>(v + (r < kLanes ? kPer * r : 0));
+  double a[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer / 2; ++q) {
+    const double2 u = p[q];
+    a[2 * q] = u.x;
+    a[2 * q + 1] = u.y;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (kPer * (kLanes - 1) + q >= Nv) a[q] = (r == kLanes - 1) ? 0.0 : a[q];
+  double s = 0.0;
+#pragma unroll
+  for (int step = 0; step < kLanes; ++step) {
+    double u = dpp_row_shr1(s);
+    if (GP::kL < 16) u = r == 0 ? 0.0 : u;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) u = u + a[q];
+    s = u;
+  }
+  return __shfl(s, kLanes - 1, GP::kL);
+}
+
+// sum_k t_k over k = 0..N-1 in order, t_k held by the owners; every lane of
+// the group gets the same value.
 template <class GP>
 __device__ double group_sum(const Grp<GP>& x, const double (&t)[GP::S]) {
   double* red = x.lds + GP::kOffRed;
@@ -68,9 +119,7 @@ __device__ double group_sum(const Grp<GP>& x, const double (&t)[GP::S]) {
   for (int m = 0; m < GP::S; ++m)
     if (owns<GP>(x, m)) red[x.sp[m]] = t[m];
   group_sync();
-  double s = 0.0;
-#pragma unroll 8
-  for (int k = 0; k < GP::N; ++k) s += red[k];
+  const double s = group_chain_sum<GP, GP::N>(x, red);
   group_sync();
   return s;
 }
@@ -136,54 +185,72 @@ __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const do
 template <class GP>
 __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>& x,
                                       const double (&y)[GP::S], double (&f)[GP::S]) {
-  constexpr int N = GP::N, NR = GP::NR, LL = GP::kL;
-  (void)LL;
+  static_assert(GP::S == 2 && GP::kOffC % 2 == 0, "two species slots per lane, aligned C");
+  constexpr int N = GP::N, LL = GP::kL;
   double* const C = x.lds + GP::kOffC;
   double* const Q = x.lds + GP::kOffQ;
+  // the operand and term tables are read from constant memory at each
+  // evaluation (vector loads, cached, issued here so that the exchanges below
+  // cover their latency), not held in registers across the integration
+  const int z0 = opaque_zero();
+  const uint32_t* const rxt = GP::kRx + z0 + x.r;
+  const uint32_t* const tct = GP::kTc + z0 + x.r;
+  uint32_t rxw[GP::R];
+#pragma unroll
+  for (int m = 0; m < GP::R; ++m) rxw[m] = rxt[m * LL];
 #pragma unroll
   for (int m = 0; m < GP::S; ++m)
     if (owns<GP>(x, m)) C[x.sp[m]] = (L.rho * y[m]) * L.iW[m];
   group_sync();
-  if (x.r == 0) {
-    double M = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < N; ++k) M += C[k];
-    C[N] = M;
-  }
-  group_sync();
+  const double M = group_chain_sum<GP, N>(x, C);
+  uint32_t tcw[GP::kTermWords];
+#pragma unroll
+  for (int w = 0; w < GP::kTermWords; ++w) tcw[w] = tct[w * LL];
 #pragma unroll
   for (int m = 0; m < GP::R; ++m) {
-    const int j = m * LL + x.r;
-    if (j < NR) {
-      uint32_t code = L.rx[m];
-      opaque(code);
-      const double ca = C[code & 0xffu], cb = C[(code >> 8) & 0xffu];
-      const double cc = C[(code >> 16) & 0xffu], cd = C[code >> 24];
-      const double q = (L.kf[m] * ca) * cb - (L.kr[m] * cc) * cd;
-      Q[j] = q;
-      Q[NR + 1 + j] = -q;
+    const int p = m * LL + x.r;
+    const uint32_t code = rxw[m];
+    const uint32_t ib = (code >> 8) & 0xffu, id = code >> 24;
+    const double ca = C[code & 0xffu], cc = C[(code >> 16) & 0xffu];
+    double cb = C[ib], cd = C[id];
+    if (m >= GP::kMSlot) {
+      // a one-species side: its second factor is [M]
+      cb = ib == (uint32_t)N ? M : cb;
+      cd = id == (uint32_t)N ? M : cd;
     }
+    const double q = (L.kf[m] * ca) * cb - (L.kr[m] * cc) * cd;
+    Q[p] = q;
+    Q[GP::kNegOff + p] = -q;
     // bound how far the scheduler moves loads ahead (register pressure)
     if (m % 2 == 1) __builtin_amdgcn_sched_barrier(0);
   }
   group_sync();
+  // each lane's signed rates: its slot-0 species' terms (padded to whole
+  // chunks with the zero), then from chunk L.bnd on its slot-1 species'; the
+  // accumulator moves to slot 0 at the end of chunk L.bnd - 1
+  double acc = 0.0, om0 = 0.0;
 #pragma unroll
-  for (int m = 0; m < GP::S; ++m) {
-    double om = 0.0;
-#pragma unroll
-    for (int t = GP::kTermOff[m]; t < GP::kTermOff[m + 1]; ++t) {
-      // term t: kTermBits-bit index into the signed rates, packed
-      // kTermsPerWord to a register; om - q is formed as om + (-q)
-      uint32_t word = L.tc[t / GP::kTermsPerWord];
-      if (t % GP::kTermsPerWord == 0) opaque(word);
-      const uint32_t code = (word >>
-                             ((t % GP::kTermsPerWord) * GP::kTermBits)) &
-                            ((1u << GP::kTermBits) - 1u);
-      om = om + Q[code];
-      if (t % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+  for (int t = 0; t < GP::kTermLen; ++t) {
+    // term t: kTermBits-bit position in the signed rates, packed
+    // kTermsPerWord to a register; om - q is formed as om + (-q)
+    const uint32_t word = tcw[t / GP::kTermsPerWord];
+    const uint32_t code = (word >> ((t % GP::kTermsPerWord) * GP::kTermBits)) &
+                          ((1u << GP::kTermBits) - 1u);
+    acc = acc + Q[code];
+    if (t % GP::kChunk == GP::kChunk - 1) {
+      const bool sw = t / GP::kChunk + 1 == L.bnd;
+      om0 = sw ? acc : om0;
+      acc = sw ? 0.0 : acc;
     }
-    f[m] = owns<GP>(x, m) ? (L.W[m] * om) * L.irho : 0.0;
+    if (t % 4 == 3) {
+      // keep the additions next to their loads (else all loads are issued
+      // first and held in registers)
+      opaque_f64(acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
+  f[0] = owns<GP>(x, 0) ? (L.W[0] * om0) * L.irho : 0.0;
+  f[1] = owns<GP>(x, 1) ? (L.W[1] * acc) * L.irho : 0.0;
 }
 
 template <class GP>
@@ -192,18 +259,31 @@ __device__ void gcopy(double (&d)[GP::S], const double (&s)[GP::S]) {
   for (int m = 0; m < GP::S; ++m) d[m] = s[m];
 }
 
+// The group drivers are state machines at right-hand-side granularity: a
+// driver always holds the argument z of its next evaluation, and advance()
+// consumes the value f(z), runs the method's arithmetic up to the next
+// evaluation it needs (or the end of the integration) and sets z again.  The
+// persistent loop evaluates every active group's f(z) at one place, so the
+// groups of a wave evaluate together whatever step, stage or power iteration
+// each is in, and a group that finishes takes a new system at the next
+// evaluation.  The operations and their order are those of the one-lane
+// drivers (rk_device.hpp), hence the same bits.
+
 // ------------------------------------------------------------------- RKCK
 template <class GP>
 struct GRkck {
   static constexpr int S = GP::S;
   typename GP::Lane L;
-  double y[S], F[S];
+  double y[S], F[S], z[S];
+  double k1[S], k2[S], k3[S], k4[S], k5[S];
   double t, h, h_want;
   int64_t attempts;
   int32_t n_acc, n_rej, n_rhs, status;
+  int32_t stage;   // the pending evaluation: 1 = f(t, y), 2..6 = stage 2..6
   bool fvalid, cut;
 
-  __device__ void begin(const Ctl& c) {
+  // Starts an integration; true when an evaluation is pending.
+  __device__ bool begin(const Grp<GP>& x, const Ctl& c) {
     t = c.t0;
     h = 0.5 * c.hmax;
     h_want = h;
@@ -212,9 +292,12 @@ struct GRkck {
     status = kSysOk;
     attempts = 0;
     n_acc = n_rej = n_rhs = 0;
+    return next_attempt(x, c);
   }
 
-  __device__ bool attempt(const Grp<GP>& x, const Ctl& c) {
+  // The start of an attempt, up to its first evaluation (false: finished).
+  __device__ bool next_attempt(const Grp<GP>& x, const Ctl& c) {
+    if (!(t < c.t1)) return false;
     if (attempts >= c.max_steps) {
       status = kSysMaxSteps;
       return false;
@@ -222,42 +305,69 @@ struct GRkck {
     h_want = h;
     h = fmin(c.t1 - t, h);
     if (!fvalid) {
-      group_rhs<GP>(L, x, y, F);
-      ++n_rhs;
-      fvalid = true;
+      gcopy<GP>(z, y);
+      stage = 1;
+      return true;
     }
-    double k1[S], k2[S], k3[S], k4[S], k5[S], z[S], f[S], yt[S], ye[S];
+    return first_stage();
+  }
+
+  __device__ bool first_stage() {
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       k1[i] = h * F[i];
       z[i] = y[i] + ck::b21 * k1[i];
     }
-    group_rhs<GP>(L, x, z, f);
+    stage = 2;
+    return true;
+  }
+
+  // Consumes f(z); false when the integration has ended.
+  __device__ bool advance(const Grp<GP>& x, const Ctl& c, const double (&f)[S]) {
+    switch (stage) {
+      case 1:
+        gcopy<GP>(F, f);
+        ++n_rhs;
+        fvalid = true;
+        return first_stage();
+      case 2:
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      k2[i] = h * f[i];
-      z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
-    }
-    group_rhs<GP>(L, x, z, f);
+        for (int i = 0; i < S; ++i) {
+          k2[i] = h * f[i];
+          z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
+        }
+        stage = 3;
+        return true;
+      case 3:
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      k3[i] = h * f[i];
-      z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
-    }
-    group_rhs<GP>(L, x, z, f);
+        for (int i = 0; i < S; ++i) {
+          k3[i] = h * f[i];
+          z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
+        }
+        stage = 4;
+        return true;
+      case 4:
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      k4[i] = h * f[i];
-      z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
-    }
-    group_rhs<GP>(L, x, z, f);
+        for (int i = 0; i < S; ++i) {
+          k4[i] = h * f[i];
+          z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
+        }
+        stage = 5;
+        return true;
+      case 5:
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      k5[i] = h * f[i];
-      z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
-             ck::b65 * k5[i];
+        for (int i = 0; i < S; ++i) {
+          k5[i] = h * f[i];
+          z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
+                 ck::b65 * k5[i];
+        }
+        stage = 6;
+        return true;
+      default:
+        break;
     }
-    group_rhs<GP>(L, x, z, f);
+    // stage 6: the trial step, its error and the controller
+    double yt[S], ye[S];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const double k6 = h * f[i];
@@ -300,7 +410,7 @@ struct GRkck {
         return false;
       }
     }
-    return t < c.t1;
+    return next_attempt(x, c);
   }
 
   __device__ void stats(int32_t (&st)[kNStats]) const {
@@ -313,11 +423,14 @@ struct GRkck {
   }
   __device__ const double (&state() const)[S] { return y; }
   __device__ double (&state())[S] { return y; }
-  // carried controller state (rows of the carry array), as the one-lane driver
-  __device__ void load_carry(const Grp<GP>&, const Ctl&, const double* carry, int64_t n,
+  // carried controller state (rows of the carry array), as the one-lane driver;
+  // applied before the first evaluation
+  __device__ bool load_carry(const Grp<GP>& x, const Ctl& c, const double* carry, int64_t n,
                              int64_t i) {
     h = carry[(int64_t)kCarryH * n + i];
     h_want = h;
+    attempts = 0;
+    return next_attempt(x, c);
   }
   __device__ void store_carry(const Grp<GP>& x, double* carry, int64_t n, int64_t i) const {
     if (x.r != 0) return;
@@ -330,40 +443,47 @@ struct GRkck {
 template <class GP>
 struct GRkc {
   static constexpr int S = GP::S, N = GP::N;
+  enum : int32_t { kPhBegin, kPhPower, kPhFirst, kPhStage, kPhError };
   typename GP::Lane L;
-  double yn[S], Fn[S], v[S];
+  double yn[S], Fn[S], v[S], y[S], w2[S], z[S];
   double t, h, h_prev, err_prev, sigma, cbrt_err_prev, h_want;
+  double hh;            // the first step's trial size
+  double p_sig, p_dyn;  // power method: last estimate, perturbation size
   int64_t nstep, attempts;
-  int32_t sr_phase;          // nstep mod sr_period
+  int32_t sr_phase;     // nstep mod sr_period
+  int32_t p_it;         // power method: iteration of the pending evaluation
+  int32_t st_j, st_m;   // stage j of m of the pending evaluation
+  int32_t phase;
   int32_t n_acc, n_rej, n_rhs, n_sr, n_pow, max_m, status;
-  bool first, have_prev, cut;
+  bool first, have_prev, cut, p_rejected, v_carried;
 
-  __device__ void begin(const Grp<GP>& x, const Ctl& c) {
+  __device__ bool begin(const Grp<GP>& x, const Ctl& c) {
     t = c.t0;
     status = kSysOk;
     attempts = 0;
     n_acc = n_rej = n_rhs = n_sr = n_pow = max_m = 0;
-    if (t < c.t1) {
-      group_rhs<GP>(L, x, yn, Fn);
-      ++n_rhs;
-    } else {
-#pragma unroll
-      for (int i = 0; i < S; ++i) Fn[i] = 0.0;
-    }
-    gcopy<GP>(v, Fn);
     h = h_prev = err_prev = sigma = cbrt_err_prev = h_want = 0.0;
     nstep = 0;
     sr_phase = 0;
     first = true;
     have_prev = false;
     cut = false;
+    v_carried = false;
+    if (t < c.t1) {
+      gcopy<GP>(z, yn);
+      phase = kPhBegin;
+      return true;
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) Fn[i] = v[i] = 0.0;
+    return false;
   }
 
-  // Nonlinear power method (Appendix), as spec_rad.
-  __device__ double spec_rad(const Grp<GP>& x, double hmax, int itmax, int& iters) {
-    double Fv[S], t2[S];
+  // Nonlinear power method (Appendix), as spec_rad: the set-up up to the
+  // first evaluation f(v).
+  __device__ void power_start(const Grp<GP>& x, bool after_reject) {
+    double t2[S];
     const double sq = sqrt(kUround);
-    const double small = 1.0 / hmax;
 #pragma unroll
     for (int i = 0; i < S; ++i) t2[i] = yn[i] * yn[i];
     double ynrm = group_sum<GP>(x, t2);
@@ -372,85 +492,86 @@ struct GRkc {
     double vnrm = group_sum<GP>(x, t2);
     ynrm = sqrt(ynrm);
     vnrm = sqrt(vnrm);
-    double dynrm;
     if (ynrm != 0.0 && vnrm != 0.0) {
-      dynrm = ynrm * sq;
-      const double r = dynrm / vnrm;
+      p_dyn = ynrm * sq;
+      const double r = p_dyn / vnrm;
 #pragma unroll
       for (int i = 0; i < S; ++i) v[i] = yn[i] + v[i] * r;
     } else if (ynrm != 0.0) {
-      dynrm = ynrm * sq;
+      p_dyn = ynrm * sq;
 #pragma unroll
       for (int i = 0; i < S; ++i) v[i] = yn[i] * (1.0 + sq);
     } else if (vnrm != 0.0) {
-      dynrm = kUround;
-      const double r = dynrm / vnrm;
+      p_dyn = kUround;
+      const double r = p_dyn / vnrm;
 #pragma unroll
       for (int i = 0; i < S; ++i) v[i] = v[i] * r;
     } else {
-      dynrm = kUround;
+      p_dyn = kUround;
 #pragma unroll
       for (int i = 0; i < S; ++i) v[i] = owns<GP>(x, i) ? kUround : 0.0;
     }
-    double sig = 0.0;
-    iters = itmax;
-    for (int it = 1; it <= itmax; ++it) {
-      group_rhs<GP>(L, x, v, Fv);
-#pragma unroll
-      for (int i = 0; i < S; ++i) t2[i] = (Fv[i] - Fn[i]) * (Fv[i] - Fn[i]);
-      double d = group_sum<GP>(x, t2);
-      d = sqrt(d);
-      const double sprev = sig;
-      sig = d / dynrm;
-      if (it >= 2 && fabs(sig - sprev) <= fmax(sig, small) * 0.01) {
-#pragma unroll
-        for (int i = 0; i < S; ++i) v[i] = v[i] - yn[i];
-        iters = it;
-        break;
-      }
-      if (d != 0.0) {
-        const double r = dynrm / d;
-#pragma unroll
-        for (int i = 0; i < S; ++i) v[i] = yn[i] + (Fv[i] - Fn[i]) * r;
-      } else {
-        const int ind = it % N;
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-          if (x.sp[i] == ind) v[i] = yn[i] - (v[i] - yn[i]);
-      }
-    }
-    return 1.2 * sig;
+    p_sig = 0.0;
+    p_it = 1;
+    p_rejected = after_reject;
+    gcopy<GP>(z, v);
+    phase = kPhPower;
   }
 
-  // One RKC step of s stages from (yn, Fn) into y, as rkc_step.
-  __device__ void step(const Grp<GP>& x, double hh, int s, double (&y)[S]) {
-    const bool tab = s <= kRkcTableS;
-    RkcCoef cf;
-    if (!tab) cf = RkcCoef(s);
-    const int row = tab ? rkc_table_row(s) - 2 : 0;
-    double wjm2[S], f[S];
-    const double mut1 = tab ? kRkcTable.mut1[s] : cf.mut1();
-    const double mh1 = mut1 * hh;
+  // One power iteration on Fv = f(v); true when the estimate is final.
+  __device__ bool power_step(const Grp<GP>& x, const Ctl& c, const double (&Fv)[S]) {
+    double t2[S];
+    ++n_rhs;
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-      wjm2[i] = yn[i];
-      y[i] = yn[i] + mh1 * Fn[i];
-    }
-    for (int j = 2; j <= s; ++j) {
-      const RkcStageCoef k = tab ? kRkcTable.st[row + j] : cf.next();
-      const double mh = k.mut * hh, gh = k.gt * hh;
-      group_rhs<GP>(L, x, y, f);
+    for (int i = 0; i < S; ++i) t2[i] = (Fv[i] - Fn[i]) * (Fv[i] - Fn[i]);
+    double d = group_sum<GP>(x, t2);
+    d = sqrt(d);
+    const double sprev = p_sig;
+    p_sig = d / p_dyn;
+    const double small = 1.0 / c.hmax;
+    if (p_it >= 2 && fabs(p_sig - sprev) <= fmax(p_sig, small) * 0.01) {
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const double wj = k.c0 * yn[i] + k.mu * y[i] + k.nu * wjm2[i] + mh * f[i] + gh * Fn[i];
-        wjm2[i] = y[i];
-        y[i] = wj;
-      }
+      for (int i = 0; i < S; ++i) v[i] = v[i] - yn[i];
+      n_pow += p_it;
+      return true;
     }
+    if (d != 0.0) {
+      const double r = p_dyn / d;
+#pragma unroll
+      for (int i = 0; i < S; ++i) v[i] = yn[i] + (Fv[i] - Fn[i]) * r;
+    } else {
+      const int ind = p_it % N;
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+        if (x.sp[i] == ind) v[i] = yn[i] - (v[i] - yn[i]);
+    }
+    if (p_it >= c.sr_itmax) {
+      n_pow += c.sr_itmax;
+      return true;
+    }
+    ++p_it;
+    gcopy<GP>(z, v);
+    return false;
   }
 
-  __device__ bool attempt(const Grp<GP>& x, const Ctl& c) {
-    const double hmax = c.hmax, hmin = c.hmin_rkc;
+  // Coefficients of stage j of an s-stage step: tabulated, or the recurrence
+  // (RkcCoef) kept in the group's norm scratch between evaluations.
+  __device__ RkcStageCoef stage_coef(const Grp<GP>& x, int s, int j) {
+    if (s <= kRkcTableS) return kRkcTable.st[rkc_table_row(s) + j - 2];
+    static_assert(sizeof(RkcCoef) <= sizeof(double) * GP::N, "recurrence fits the scratch");
+    RkcCoef* keep = reinterpret_cast<RkcCoef*>(x.lds + GP::kOffRed);
+    RkcCoef cf = *keep;
+    const RkcStageCoef k = cf.next();
+    group_sync();
+    if (x.r == 0) *keep = cf;
+    group_sync();
+    return k;
+  }
+
+  // The attempt from its start (after an accepted step, a rejection's power
+  // method, or the first evaluation) up to its first evaluation.
+  __device__ bool next_attempt(const Grp<GP>& x, const Ctl& c) {
+    if (!(t < c.t1)) return false;
     if (attempts >= c.max_steps) {
       status = kSysMaxSteps;
       return false;
@@ -458,44 +579,113 @@ struct GRkc {
     h_want = h;
     if (1.1 * h >= fabs(c.t1 - t)) h = fabs(c.t1 - t);
     if (sr_phase == 0) {
-      int it;
-      sigma = spec_rad(x, hmax, c.sr_itmax, it);
-      ++n_sr;
-      n_pow += it;
-      n_rhs += it;
+      power_start(x, false);
+      return true;
     }
-    double y[S], F1[S], e2[S];
+    return after_power(x, c);
+  }
+
+  // The attempt after its spectral radius: the first step's trial evaluation,
+  // or the stages.
+  __device__ bool after_power(const Grp<GP>& x, const Ctl& c) {
     if (first) {
-      double hh = hmax;
+      hh = c.hmax;
       if (sigma * hh > 1.0) hh = 1.0 / sigma;
-      hh = fmax(hh, hmin);
+      hh = fmax(hh, c.hmin_rkc);
 #pragma unroll
-      for (int i = 0; i < S; ++i) y[i] = yn[i] + hh * Fn[i];
-      group_rhs<GP>(L, x, y, F1);
-      ++n_rhs;
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const double est = (F1[i] - Fn[i]) / (c.atol + c.rtol * fabs(yn[i]));
-        e2[i] = est * est;
-      }
-      const double e = group_sum<GP>(x, e2);
-      const double err0 = hh * sqrt(e / (double)N);
-      if (kP1 * hh < hmax * sqrt(err0))
-        hh = fmax(kP1 * hh / sqrt(err0), hmin);
-      else
-        hh = hmax;
-      h = hh;
-      first = false;
+      for (int i = 0; i < S; ++i) z[i] = yn[i] + hh * Fn[i];
+      phase = kPhFirst;
+      return true;
     }
-    const int m = rkc_stage_count(h, sigma, c.mmax);
-    max_m = max(max_m, m);
-    step(x, h, m, y);
-    group_rhs<GP>(L, x, y, F1);
-    n_rhs += m;
-    ++attempts;
+    return start_stages(x, c);
+  }
+
+  __device__ bool start_stages(const Grp<GP>& x, const Ctl& c) {
+    st_m = rkc_stage_count(h, sigma, c.mmax);
+    max_m = max(max_m, st_m);
+    double mut1;
+    if (st_m <= kRkcTableS) {
+      mut1 = kRkcTable.mut1[st_m];
+    } else {
+      const RkcCoef cf(st_m);
+      mut1 = cf.mut1();
+      group_sync();
+      if (x.r == 0) *reinterpret_cast<RkcCoef*>(x.lds + GP::kOffRed) = cf;
+      group_sync();
+    }
+    const double mh1 = mut1 * h;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-      double est = 0.8 * (yn[i] - y[i]) + 0.4 * h * (Fn[i] + F1[i]);
+      w2[i] = yn[i];
+      y[i] = yn[i] + mh1 * Fn[i];
+    }
+    st_j = 2;
+    gcopy<GP>(z, y);
+    phase = kPhStage;
+    return true;
+  }
+
+  // Consumes f(z); false when the integration has ended.
+  __device__ bool advance(const Grp<GP>& x, const Ctl& c, const double (&f)[S]) {
+    switch (phase) {
+      case kPhBegin:
+        gcopy<GP>(Fn, f);
+        ++n_rhs;
+        if (!v_carried) gcopy<GP>(v, Fn);
+        return next_attempt(x, c);
+      case kPhPower:
+        if (!power_step(x, c, f)) return true;
+        sigma = 1.2 * p_sig;
+        ++n_sr;
+        if (p_rejected) {
+          if (!(h >= c.hmin_rkc)) {
+            status = kSysHmin;
+            return false;
+          }
+          return next_attempt(x, c);
+        }
+        return after_power(x, c);
+      case kPhFirst: {
+        ++n_rhs;
+        double e2[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double est = (f[i] - Fn[i]) / (c.atol + c.rtol * fabs(yn[i]));
+          e2[i] = est * est;
+        }
+        const double e = group_sum<GP>(x, e2);
+        const double err0 = hh * sqrt(e / (double)N);
+        if (kP1 * hh < c.hmax * sqrt(err0))
+          hh = fmax(kP1 * hh / sqrt(err0), c.hmin_rkc);
+        else
+          hh = c.hmax;
+        h = hh;
+        first = false;
+        return start_stages(x, c);
+      }
+      case kPhStage: {
+        const RkcStageCoef k = stage_coef(x, st_m, st_j);
+        const double mh = k.mut * h, gh = k.gt * h;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          const double wj = k.c0 * yn[i] + k.mu * y[i] + k.nu * w2[i] + mh * f[i] + gh * Fn[i];
+          w2[i] = y[i];
+          y[i] = wj;
+        }
+        if (++st_j > st_m) phase = kPhError;
+        gcopy<GP>(z, y);
+        return true;
+      }
+      default:
+        break;
+    }
+    // kPhError: f = f(w_s), the error estimate and the controller
+    n_rhs += st_m;
+    ++attempts;
+    double e2[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      double est = 0.8 * (yn[i] - y[i]) + 0.4 * h * (Fn[i] + f[i]);
       est = est / (c.atol + c.rtol * fmax(fabs(y[i]), fabs(yn[i])));
       e2[i] = est * est;
     }
@@ -503,45 +693,37 @@ struct GRkc {
     if (err > 1.0 || !crm::is_finite(err)) {
       ++n_rej;
       h = crm::is_finite(err) ? 0.8 * h / crm::pow_third_one(err) : kP1 * h;
-      int it;
-      sigma = spec_rad(x, hmax, c.sr_itmax, it);
-      ++n_sr;
-      n_pow += it;
-      n_rhs += it;
-      if (!(h >= hmin)) {
-        status = kSysHmin;
-        return false;
-      }
-    } else {
-      cut = h < h_want;
-      t += h;
-      ++nstep;
-      if (++sr_phase == c.sr_period) sr_phase = 0;
-      ++n_acc;
-      double cbrt_err, err23;
-      crm::pow_third_pair(err, cbrt_err, err23);
-      double fac = 10.0;
-      if (!have_prev) {
-        if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
-      } else {
-        const double t1 = 0.8 * h * cbrt_err_prev;
-        const double t2 = h_prev * err23;
-        if (t1 < fac * t2) fac = t1 / t2;
-      }
-      err_prev = err;
-      cbrt_err_prev = cbrt_err;
-      h_prev = h;
-      have_prev = true;
-      gcopy<GP>(yn, y);
-      gcopy<GP>(Fn, F1);
-      h = h * fmax(kP1, fac);
-      h = fmax(hmin, fmin(hmax, h));
-      if (!group_all_finite<GP>(x, yn)) {
-        status = kSysNonFinite;
-        return false;
-      }
+      power_start(x, true);
+      return true;
     }
-    return t < c.t1;
+    cut = h < h_want;
+    t += h;
+    ++nstep;
+    if (++sr_phase == c.sr_period) sr_phase = 0;
+    ++n_acc;
+    double cbrt_err, err23;
+    crm::pow_third_pair(err, cbrt_err, err23);
+    double fac = 10.0;
+    if (!have_prev) {
+      if (0.8 < fac * cbrt_err) fac = 0.8 / cbrt_err;
+    } else {
+      const double t1 = 0.8 * h * cbrt_err_prev;
+      const double t2 = h_prev * err23;
+      if (t1 < fac * t2) fac = t1 / t2;
+    }
+    err_prev = err;
+    cbrt_err_prev = cbrt_err;
+    h_prev = h;
+    have_prev = true;
+    gcopy<GP>(yn, y);
+    gcopy<GP>(Fn, f);
+    h = h * fmax(kP1, fac);
+    h = fmax(c.hmin_rkc, fmin(c.hmax, h));
+    if (!group_all_finite<GP>(x, yn)) {
+      status = kSysNonFinite;
+      return false;
+    }
+    return next_attempt(x, c);
   }
 
   __device__ void stats(int32_t (&st)[kNStats]) const {
@@ -554,7 +736,8 @@ struct GRkc {
   }
   __device__ const double (&state() const)[S] { return yn; }
   __device__ double (&state())[S] { return yn; }
-  __device__ void load_carry(const Grp<GP>& x, const Ctl& c, const double* carry, int64_t n,
+  // carried controller state, applied before the first evaluation f(t0, y0)
+  __device__ bool load_carry(const Grp<GP>& x, const Ctl& c, const double* carry, int64_t n,
                              int64_t i) {
     h = carry[(int64_t)kCarryH * n + i];
     h_prev = carry[(int64_t)kCarryHPrev * n + i];
@@ -570,6 +753,8 @@ struct GRkc {
       const int k = x.sp[m];
       v[m] = k >= 0 ? carry[(int64_t)(kCarryRows + k) * n + i] : 0.0;
     }
+    v_carried = true;
+    return true;   // the pending evaluation f(t0, y0) stays
   }
   __device__ void store_carry(const Grp<GP>& x, double* carry, int64_t n, int64_t i) const {
 #pragma unroll
@@ -591,7 +776,8 @@ struct GRkc {
 template <class GP, int Method>
 using GDriverState = typename std::conditional<Method == kMethodRkck, GRkck<GP>, GRkc<GP>>::type;
 
-// A group's integration of one system: start / attempt / finish as Driver.
+// A group's integration of one system: start (true while an evaluation is
+// pending), advance (consumes f(z)), finish.
 template <class GP, int Method>
 struct GDriver {
   GDriverState<GP, Method> D;
@@ -605,14 +791,15 @@ struct GDriver {
       const int k = x.sp[m];
       y[m] = k >= 0 ? y0[(int64_t)k * n + i] : 0.0;
     }
-    if constexpr (Method == kMethodRkck)
-      D.begin(c);
-    else
-      D.begin(x, c);
-    if (carry && carry[(int64_t)kCarryValid * n + i] != 0.0) D.load_carry(x, c, carry, n, i);
-    return D.t < c.t1;
+    bool pending = D.begin(x, c);
+    if (pending && carry && carry[(int64_t)kCarryValid * n + i] != 0.0)
+      pending = D.load_carry(x, c, carry, n, i);
+    return pending;
   }
-  __device__ bool attempt(const Ctl& c, const Grp<GP>& x) { return D.attempt(x, c); }
+  __device__ const double (&arg() const)[GP::S] { return D.z; }
+  __device__ bool advance(const Ctl& c, const Grp<GP>& x, const double (&f)[GP::S]) {
+    return D.advance(x, c, f);
+  }
   __device__ void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
                          const Grp<GP>& x, double* carry = nullptr) const {
     const auto& y = D.state();
@@ -636,6 +823,8 @@ struct GDriver {
 
 template <class GP>
 __device__ Grp<GP> group_of(double* lds) {
+  static_assert(GP::kLdsPerSystem % 2 == 0 && GP::kOffRed % 2 == 0,
+                "16-byte aligned group areas (chain sums read pairs)");
   const int lane = threadIdx.x;
   const int g = lane / GP::kL;
   const unsigned long long ones =
@@ -659,7 +848,8 @@ constexpr int group_lds_doubles() {
 }
 
 // Persistent loop at group granularity: as persistent_loop, with a group of
-// kL lanes as the unit that takes a system; the refill threshold counts lanes.
+// kL lanes as the unit that takes a system and one right-hand-side
+// evaluation as the unit of progress; the refill threshold counts lanes.
 template <class GP, int Method>
 __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n, const double* y0,
                                       double* y1, const double* g, const Ctl& c, int32_t* status,
@@ -697,9 +887,13 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
       }
     }
     if (!__ballot(!retired)) break;
-    if (active && !D.attempt(c, x)) {
-      D.finish(n, i, y1, status, stats, x, carry);
-      active = false;
+    if (active) {
+      double f[GP::S];
+      group_rhs<GP>(D.D.L, x, D.arg(), f);
+      if (!D.advance(c, x, f)) {
+        D.finish(n, i, y1, status, stats, x, carry);
+        active = false;
+      }
     }
   }
 }
@@ -728,7 +922,7 @@ __attribute__((amdgpu_waves_per_eu(GroupWavesPerEu<GP, Method>::value))) void gr
     const double* __restrict__ g, Ctl c, int32_t* __restrict__ status,
     int32_t* __restrict__ stats, unsigned long long* queue, const int32_t* __restrict__ order,
     double* __restrict__ carry) {
-  __shared__ double lds[group_lds_doubles<GP>()];
+  __shared__ __attribute__((aligned(16))) double lds[group_lds_doubles<GP>()];
   group_persistent_loop<GP, Method>(prm, n, y0, y1, g, c, status, stats, queue, lds, order,
                                     carry);
 }

@@ -91,7 +91,7 @@ struct PleiadesGroup {
   static constexpr bool kOwnRhs = true;
   static constexpr int kOffPos = 0;               // x_1..x_7, y_1..y_7
   static constexpr int kOffPair = 14;             // 1 / r_ij at i * 7 + j
-  static constexpr int kOffRed = kOffPair + 49;   // norm scratch, N doubles
+  static constexpr int kOffRed = kOffPair + 50;   // norm scratch, N doubles (16-byte aligned)
   static constexpr int kLdsPerSystem = kOffRed + N;
   static constexpr int kSp[S * kL] = {0,  1,  2,  3,  4,  5,  6,  -1,     // x_r
                                       7,  8,  9,  10, 11, 12, 13, -1,     // y_r
