@@ -484,6 +484,7 @@ def group_source(net, tag: str, lanes: int | None = None) -> str:
         bnd.append(len(l0) // chunk)
     tot = max(len(q) for q in seqs)
     tot += (-tot) % chunk
+    assert tot // chunk <= 64
     seqs = [q + [sentinel] * (tot - len(q)) for q in seqs]
     bits = (neg + R * L).bit_length()
     per_word = 32 // bits
@@ -525,6 +526,8 @@ struct GNet {{
 {_table("kRx", "uint32_t", rx)}
 {_table("kTc", "uint32_t", tc)}
 {_table("kBnd", "int", bnd)}
+  // chunks at whose end some lane moves its accumulator to slot 0 (bit c)
+  static constexpr uint64_t kSwitchChunks = {sum(1 << (b - 1) for b in set(bnd) if b > 0)}ull;
   struct Lane {{
     double kf[R], kr[R];
     uint32_t rx[R];

@@ -26,8 +26,9 @@
 // m L + r, -1 for none), kRx (packed operand species of each position's
 // reaction, [M] as index N), kTc (each lane's signed rate positions, packed:
 // its slot-0 species' list padded with the zero to whole chunks of kChunk
-// terms, then its slot-1 species' list, kTermLen in all) and kBnd (the chunks
-// of the slot-0 list), Params, Lane, init(Lane&, prm, g, i, n, x).
+// terms, then its slot-1 species' list, kTermLen in all), kBnd (the chunks
+// of the slot-0 list) and kSwitchChunks (the chunks at whose end some lane
+// switches), Params, Lane, init(Lane&, prm, g, i, n, x).
 #pragma once
 
 #include "rk_device.hpp"
@@ -237,7 +238,7 @@ __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>&
     const uint32_t code = (word >> ((t % GP::kTermsPerWord) * GP::kTermBits)) &
                           ((1u << GP::kTermBits) - 1u);
     acc = acc + Q[code];
-    if (t % GP::kChunk == GP::kChunk - 1) {
+    if (t % GP::kChunk == GP::kChunk - 1 && ((GP::kSwitchChunks >> (t / GP::kChunk)) & 1)) {
       const bool sw = t / GP::kChunk + 1 == L.bnd;
       om0 = sw ? acc : om0;
       acc = sw ? 0.0 : acc;
