@@ -332,17 +332,27 @@ def ragged_bench(args):
     best = {9: dict(schedule=1, cost_order=1), 13: dict(schedule=1, cost_order=1),
             32: dict(schedule=3), 53: dict(schedule=3)}
 
+    per_network_s = {}
+
     def run_separate(n_sub):
         reset()
         outs = [torch.empty_like(y) for y in ys]
+        ev = []
         t = time.perf_counter()
         for j in range(n_sub):
             for k, (p, y, g) in enumerate(zip(probs, ys, gs)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
                 rk.integrate_rkc(p, y, g, j * dt, (j + 1) * dt, rtol, atol, out=y, status=st[k],
                                  stats=stats[k], **best[sizes[k]])
+                e1.record()
+                ev.append((sizes[k], e0, e1))
         torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t
+        for size, e0, e1 in ev:
+            per_network_s[str(size)] = per_network_s.get(str(size), 0.0) + e0.elapsed_time(e1) / 1e3
         del outs
-        return time.perf_counter() - t
+        return elapsed
 
     times = {}
     for k in range(args.warmup):
@@ -362,7 +372,8 @@ def ragged_bench(args):
         times["separate_best"] = run_separate(K)
         same = all(np.array_equal(a, b.cpu().numpy()) for a, b in zip(final, ys))
         log(f"bench: separate launches on each network's best schedule {times['separate_best']:.3f}"
-            f" s, same bits as persistent: {same}")
+            f" s, same bits as persistent: {same}; per network (s): "
+            + ", ".join(f"{k} species {v:.3f}" for k, v in per_network_s.items()))
     if G > 0:
         gate["substeps"] = G
         gate["persistent_s"] = run("persistent", G, use_graph=True, **tuned)
@@ -404,7 +415,8 @@ def ragged_bench(args):
                        **{f"{m}_s": times[m] for m in times if m != "persistent"},
                        "speedup_vs_separate_best": (times["separate_best"] / tp
                                                     if "separate_best" in times else None),
-                       "separate_best_schedules": {str(k): v for k, v in best.items()}},
+                       "separate_best_schedules": {str(k): v for k, v in best.items()},
+                       "separate_best_per_network_s": per_network_s or None},
         "gate": gate,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,

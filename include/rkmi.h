@@ -149,9 +149,12 @@ int rk_problem_create_mass_action(const rk_mech_desc *desc, rk_problem *out);
  *             with k_f,j = exp(lnA_j + beta_j ln T - Ea_j / T) at the current T),
  *   dT/dt   = -(sum_k e_k omega_k W_k) / (rho c_v),  c_v = sum_k Y_k c_v,k(T),
  *   e_k(T)  = u0_k + (cv0_k + cv1_k T) T,  c_v,k(T) = cv0_k + 2 cv1_k T
- * (per unit mass; u0, cv0, cv1: host arrays of n_sp, copied).  Compiled for
- * networks of up to 15 species whose topology the code generator was given
- * with the energy equation; RK_EUNSUPPORTED otherwise.  No adjoint. */
+ * (per unit mass; u0, cv0, cv1: host arrays of n_sp, copied).  Available for
+ * the topologies the code generator was given with the energy equation
+ * (RK_EUNSUPPORTED otherwise): up to 15 species on the one-lane kernels of
+ * every schedule; above, the group kernels (32 lanes per system) run under
+ * every schedule and need the queue workspace of rk_workspace_bytes.  No
+ * adjoint. */
 int rk_problem_create_mass_action_thermal(const rk_mech_desc *desc, const double *u0,
                                           const double *cv0, const double *cv1,
                                           rk_problem *out);
@@ -286,10 +289,12 @@ int rk_integrate_rkc_carry(rk_problem p, int64_t n_sys, const double *y0, double
  * A forward call records a tape (device memory the caller allocates): per
  * system the accepted-step count, each accepted step's (h, s) (s = 6 for
  * RKCK), and the state every ckpt_every accepted steps.  Layout, for n = n_sys, C = max_accepted,
- * K = ckpt_every:
+ * K = ckpt_every, each system's records contiguous:
  *   int32 count[n]          (-1: more than C accepted steps; no gradient)
- *   double h[C][n], int32 s[C][n], double y[C / K + 1][N][n]
+ *   double h[n][Hs], int32 s[n][Hs]   (step k of system i at [i][k])
+ *   double y[n][Cs]                   (checkpoint c of system i at [i][c N .. c N + N - 1])
  *   the cost order's working area (seven int32 per system and 32 KiB)
+ * with Hs = C and Cs = (C / K + 1) N, each rounded up to a multiple of 16, and
  * each array starting on a 256-byte boundary.  The reverse call recomputes
  * each segment of K steps from its checkpoint and each step's stages, and
  * carries lambda = dL/dy(t1) back to dL/dy(t0).  The same n_sys, g,

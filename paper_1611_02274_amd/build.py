@@ -24,8 +24,9 @@ ARCH = "gfx950"
 COMPILED_NETWORKS = (9, 13, 32, 53)
 # Ragged batches compiled as one kernel (species counts, in order).
 COMPILED_BATCHES = ((9, 13, 32, 53),)
-# Networks also compiled with the energy equation (state T, Y; up to 15 species).
-COMPILED_THERMAL = (9, 13)
+# Networks also compiled with the energy equation (state T, Y): up to 15 species
+# with the one-lane kernels, above on the group schedule.
+COMPILED_THERMAL = (9, 13, 32, 53)
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -354,6 +354,107 @@ extern "C" int64_t rkmi_gen_{tag}_workspace(int method, int schedule, int64_t n)
     return header, source
 
 
+def thermal_group_source(net, tag: str) -> tuple[str, str]:
+    """The network with the energy equation on the group schedule (32 lanes
+    per system, rk_group.hpp group_rhs_thermal): unknowns (T, Y_1..Y_N) over the
+    lanes' slots, the rate coefficients k_f,j(T) formed by each position's lane
+    at every evaluation, the species part as the isothermal group right-hand
+    side, and dT/dt from two species sums passed along the chain of lanes.
+    Same operations in the same order as the reference evaluation."""
+    n, nr = net.n_sp, net.n_rx
+    G = _group_layout(net, 32, thermal=True)
+    header = f"""// Generated by paper_1611_02274_amd/codegen.py -- do not edit.
+// Mass-action network with the energy equation on the group schedule: {n} species
+// + T, {nr} reversible reactions (topology {tag}).
+#pragma once
+
+#include "../rk_launch.hpp"
+#include "../rk_group.hpp"
+
+namespace rkmi {{
+namespace gen_{tag} {{
+
+struct GNet {{
+  static constexpr bool kThermal = true;
+  static constexpr int NS = {n};
+  static constexpr int N = NS + 1;    // unknowns: T, then the species
+  static constexpr int NR = {nr};
+  static constexpr int kL = {G["L"]};
+  static constexpr int kGroupLanes = {G["L"]};
+  static constexpr bool kColumns = false;
+  static constexpr int kLaneDoubles = 0;
+  static constexpr int kWavesPerEuRkc = 2;
+  static constexpr int kWavesPerEuRkck = 2;
+  static constexpr int S = {G["S"]};
+  static constexpr int R = {G["R"]};
+  static constexpr int kMSlot = {G["m_first"]};   // first slot that may hold a [M] reaction
+  static constexpr int kOffC = 0;
+  static constexpr int kOffT = NS + 1;            // T, written by its owner
+  static constexpr int kOffQ = {G["off_q"]};
+  static constexpr int kSentinel = {G["sentinel"]};
+  static constexpr int kNegOff = {G["neg"]};
+  static constexpr int kOffRed = {G["off_red"]};
+  static constexpr int kOffE1 = {G["off_e1"]};   // the energy sum's terms (after the RKC coefficients)
+  static constexpr int kOffE2 = {G["off_e2"]};   // the heat capacity's terms
+  static constexpr int kLdsPerSystem = {G["lds_per_system"]};
+  static constexpr int kTermBits = {G["bits"]};
+  static constexpr int kTermsPerWord = {G["per_word"]};
+  static constexpr int kTermWords = {G["n_words"]};
+  static constexpr int kTermLen = {G["tot"]};
+  static constexpr int kChunk = {G["chunk"]};
+  // uniform data: [lnA | beta | Ea | 1/K | W | 1/W | u0 | cv0 | cv1]
+  using Params = const double*;
+{_group_tables(G)}
+  struct Lane {{
+    const double* prm;   // the uniform data (rate parameters read at every evaluation)
+    double W[S], iW[S], u0[S], cv0[S], cv1[S];
+    double rho, irho;
+    int bnd;   // chunks of the slot-0 list
+  }};
+  __device__ static void init(Lane& L, const Params& p, const double* __restrict__ g, int64_t i,
+                              int64_t, const Grp<GNet>& x) {{
+    L.prm = p;
+#pragma unroll
+    for (int m = 0; m < S; ++m) {{
+      const int k = x.sp[m] - 1;   // species of the slot (T and empty slots: none)
+      const bool sp = k >= 0;
+      L.W[m] = sp ? p[4 * NR + k] : 0.0;
+      L.iW[m] = sp ? p[4 * NR + NS + k] : 0.0;
+      L.u0[m] = sp ? p[4 * NR + 2 * NS + k] : 0.0;
+      L.cv0[m] = sp ? p[4 * NR + 3 * NS + k] : 0.0;
+      L.cv1[m] = sp ? p[4 * NR + 4 * NS + k] : 0.0;
+    }}
+    L.rho = g[i];
+    L.irho = 1.0 / L.rho;
+    L.bnd = kBnd[x.r];
+    // the zero that pads the term sequences
+    if (x.r == 0) x.lds[kOffQ + kSentinel] = 0.0;
+  }}
+}};
+
+}}  // namespace gen_{tag}
+}}  // namespace rkmi
+"""
+    source = f"""// Generated by paper_1611_02274_amd/codegen.py -- do not edit.
+// Launchers of the {n}-species network with the energy equation (topology {tag}): the
+// group kernels under every schedule; no host build of the per-system code.
+#include "net_{tag}.hpp"
+
+extern "C" int rkmi_gen_{tag}_launch(const rkmi::LaunchArgs* a, void* s) {{
+  return rkmi::launch_group_only<rkmi::gen_{tag}::GNet>(a, s);
+}}
+
+extern "C" int rkmi_gen_{tag}_host(const rkmi::LaunchArgs*) {{
+  return rkmi::kLaunchInvalid;
+}}
+
+extern "C" int64_t rkmi_gen_{tag}_workspace(int, int, int64_t n) {{
+  return n > 0 ? (int64_t)rkmi::kQueueBytes : 0;
+}}
+"""
+    return header, source
+
+
 def _species_terms(net):
     """Per species, the signed rates of its omega sum in evaluation order:
     reaction by reaction, reactant slots (subtract) before product slots (add).
@@ -379,6 +480,9 @@ def _table(name, ctype, values, per_line=16):
 # Group variants: a lane's species list is consumed in chunks of this many
 # terms; its first species' list is padded to a whole number of chunks.
 GROUP_TERM_CHUNK = 4
+# doubles of the group scratch that hold the RKC stage recurrence (RkcCoef, 11
+# doubles) between evaluations for stage counts above the tabulated ones
+GROUP_COEF_DOUBLES = 12
 
 
 def _group_positions(net, L, R):
@@ -436,18 +540,15 @@ def _group_species(lens, L, chunk):
     return sp
 
 
-def group_source(net, tag: str, lanes: int | None = None) -> str:
-    """The group variant of a network (kernels of rk_group.hpp): lane r of a
-    group of `lanes` computes the rates of progress at its positions
-    p = m*lanes + r (_group_positions) and owns the species of its two slots
-    (_group_species); per lane: the species of each slot, the packed operand
-    species of each position's reaction, and the signed rate positions of its
-    species' sums in reaction order (slot 0's list, padded to whole chunks,
-    then slot 1's), packed into registers."""
+def _group_layout(net, L, thermal=False):
+    """The group layout of a network (rk_group.hpp): reaction positions,
+    operand codes, the unknowns of each lane's slots (isothermal: species k
+    is unknown k; with the energy equation T is unknown 0 and species k is
+    unknown 1 + k), the LDS area and each lane's packed term sequence."""
     n, nr = net.n_sp, net.n_rx
-    L = lanes or group_lanes(n)
-    S, R = -(-n // L), -(-nr // L)
-    assert S == 2, "group variants hold two species per lane"
+    nu = n + 1 if thermal else n          # unknowns
+    S, R = -(-nu // L), -(-nr // L)
+    assert S == 2, "group variants hold two unknowns per lane"
     assert n < 255, "species indices are packed in bytes"
     chunk = GROUP_TERM_CHUNK
     pos_of, rx_of, m_first = _group_positions(net, L, R)
@@ -462,16 +563,25 @@ def group_source(net, tag: str, lanes: int | None = None) -> str:
             rx.append(a | b << 8 | c << 16 | d << 24)
         else:
             rx.append(0)
-    # LDS area of a system (doubles): C [0, N] | rates +q at kOffQ + p, p < R*L,
-    # the zero at kOffQ + R*L, norm scratch (N, 16-byte aligned) | -q at
+    # LDS area of a system (doubles): C [0, NS] (C_N the [M] operand's place;
+    # with the energy equation T at NS + 1) | rates +q at kOffQ + p, p < R*L,
+    # the zero at kOffQ + R*L, scratch (16-byte aligned: the norms over the
+    # unknowns; with the energy equation also two species sums) | -q at
     # kOffQ + kNegOff + p
-    off_q = n + 1 + (n + 1) % 2
+    c_len = n + (2 if thermal else 1)
+    off_q = c_len + c_len % 2
     off_red = off_q + R * L + 1 + (off_q + R * L + 1) % 2
-    neg = off_red - off_q + n
+    # with the energy equation the two species rows follow the RKC recurrence's
+    # coefficients, which stay in the scratch across evaluations
+    off_e1 = off_red + GROUP_COEF_DOUBLES
+    off_e2 = off_e1 + n + n % 2
+    red_len = max(nu, off_e2 + n + n % 2 - off_red) if thermal else nu
+    neg = off_red - off_q + red_len
     lds_per_system = off_q + neg + R * L
     lds_per_system += lds_per_system % 2
     sentinel = R * L
-    terms = [[pos_of[c >> 1] + neg * (c & 1) for c in lst] for lst in _species_terms(net)]
+    sterms = [[pos_of[c >> 1] + neg * (c & 1) for c in lst] for lst in _species_terms(net)]
+    terms = ([[]] + sterms) if thermal else sterms     # per unknown
     lens = [len(t) for t in terms]
     sp = _group_species(lens, L, chunk)
     seqs, bnd = [], []
@@ -493,6 +603,40 @@ def group_source(net, tag: str, lanes: int | None = None) -> str:
     for r in range(L):
         for t, code in enumerate(seqs[r]):
             tc[(t // per_word) * L + r] |= code << ((t % per_word) * bits)
+    return dict(n=n, nr=nr, nu=nu, L=L, S=S, R=R, m_first=m_first, rx=rx, rx_of=rx_of,
+                off_q=off_q, off_red=off_red, off_e1=off_e1, off_e2=off_e2, neg=neg,
+                lds_per_system=lds_per_system,
+                sentinel=sentinel, sp=sp, bnd=bnd, tot=tot, bits=bits, per_word=per_word,
+                n_words=n_words, tc=tc, chunk=chunk,
+                switch=sum(1 << (b - 1) for b in set(bnd) if b > 0))
+
+
+def _group_tables(G) -> str:
+    return f"""{_table("kSp", "int", G["sp"])}
+{_table("kRxOf", "int16_t", G["rx_of"])}
+{_table("kRx", "uint32_t", G["rx"])}
+{_table("kTc", "uint32_t", G["tc"])}
+{_table("kBnd", "int", G["bnd"])}
+  // chunks at whose end some lane moves its accumulator to slot 0 (bit c)
+  static constexpr uint64_t kSwitchChunks = {G["switch"]}ull;"""
+
+
+def group_source(net, tag: str, lanes: int | None = None) -> str:
+    """The group variant of a network (kernels of rk_group.hpp): lane r of a
+    group of `lanes` computes the rates of progress at its positions
+    p = m*lanes + r (_group_positions) and owns the species of its two slots
+    (_group_species); per lane: the species of each slot, the packed operand
+    species of each position's reaction, and the signed rate positions of its
+    species' sums in reaction order (slot 0's list, padded to whole chunks,
+    then slot 1's), packed into registers."""
+    n, nr = net.n_sp, net.n_rx
+    L = lanes or group_lanes(n)
+    G = _group_layout(net, L)
+    S, R, m_first = G["S"], G["R"], G["m_first"]
+    off_q, sentinel, neg, off_red = G["off_q"], G["sentinel"], G["neg"], G["off_red"]
+    lds_per_system, bits, per_word, n_words = (G["lds_per_system"], G["bits"], G["per_word"],
+                                               G["n_words"])
+    tot, chunk = G["tot"], G["chunk"]
     return f"""
 // Group variant: {L} lanes per system (rk_group.hpp).
 struct GNet {{
@@ -521,13 +665,7 @@ struct GNet {{
   static constexpr int kTermLen = {tot};
   static constexpr int kChunk = {chunk};
   using Params = const double*;
-{_table("kSp", "int", sp)}
-{_table("kRxOf", "int16_t", rx_of)}
-{_table("kRx", "uint32_t", rx)}
-{_table("kTc", "uint32_t", tc)}
-{_table("kBnd", "int", bnd)}
-  // chunks at whose end some lane moves its accumulator to slot 0 (bit c)
-  static constexpr uint64_t kSwitchChunks = {sum(1 << (b - 1) for b in set(bnd) if b > 0)}ull;
+{_group_tables(G)}
   struct Lane {{
     double kf[R], kr[R];
     uint32_t rx[R];
@@ -765,7 +903,8 @@ def generate(nets, out_dir: str = GEN_DIR, batches=(), thermal=()) -> list[str]:
     for net in thermal:
         tag = tag_of(net) + THERMAL_SUFFIX
         tentries.append((tag, net))
-        header, source = thermal_source(net, tag)
+        header, source = (thermal_source(net, tag) if net.n_sp + 1 <= REGISTER_SPECIES_LIMIT
+                          else thermal_group_source(net, tag))
         keep.add(os.path.basename(_write(os.path.join(out_dir, f"net_{tag}.hpp"), header)))
         paths.append(_write(os.path.join(out_dir, f"net_{tag}.hip"), source))
     for net in nets:

@@ -36,33 +36,45 @@ namespace rkmi {
 
 enum : int32_t { kSysTape = 4 };
 
-// Tape layout for n systems, cap steps, period K, N unknowns:
-//   count int32 [n] | h double [cap][n] | s int32 [cap][n] | y double [cap/K + 1][N][n]
+// Tape layout for n systems, cap steps, period K, N unknowns, each system's
+// records contiguous (a lane reads its own steps in sequence, so one cache
+// line serves 16 steps whichever systems the lanes of a wave hold):
+//   count int32 [n] | h double [n][hs] | s int32 [n][hs] | y double [n][cs]
 //   | the cost order's working area (an order_layout from off_order)
+// with hs = cap and cs = (cap/K + 1) N, each rounded up to a multiple of 16;
+// system i's checkpoint c is y[i][c N .. c N + N - 1].
 struct TapeLayout {
   size_t off_h, off_s, off_ckpt, off_order, bytes;
+  int64_t hs, cs;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int64_t kTapeRowAlign = 16;
+
 inline TapeLayout tape_layout(int64_t n, int64_t cap, int32_t K, int N) {
   TapeLayout t;
+  t.hs = (cap + kTapeRowAlign - 1) / kTapeRowAlign * kTapeRowAlign;
+  t.cs = ((cap / K + 1) * N + kTapeRowAlign - 1) / kTapeRowAlign * kTapeRowAlign;
   t.off_h = align256(sizeof(int32_t) * (size_t)n);
-  t.off_s = t.off_h + align256(sizeof(double) * (size_t)cap * (size_t)n);
-  t.off_ckpt = t.off_s + align256(sizeof(int32_t) * (size_t)cap * (size_t)n);
-  t.off_order = align256(t.off_ckpt + sizeof(double) * (size_t)(cap / K + 1) * (size_t)N *
-                                           (size_t)n);
+  t.off_s = t.off_h + align256(sizeof(double) * (size_t)t.hs * (size_t)n);
+  t.off_ckpt = t.off_s + align256(sizeof(int32_t) * (size_t)t.hs * (size_t)n);
+  t.off_order = align256(t.off_ckpt + sizeof(double) * (size_t)t.cs * (size_t)n);
   t.bytes = t.off_order + order_layout(0, n).bytes;
   return t;
 }
 
 struct TapeView {
   int32_t* count;   // accepted steps per system, -1 when they exceeded cap
-  double* h;        // [cap][n]
-  int32_t* s;       // [cap][n]
-  double* ckpt;     // [cap/K + 1][N][n]
-  int64_t n, cap;
+  double* h;        // [n][hs]
+  int32_t* s;       // [n][hs]
+  double* ckpt;     // [n][cs]
+  int64_t n, cap, hs, cs;
   int32_t K;
+  RKMI_HD double hstep(int64_t i, int64_t k) const { return h[i * hs + k]; }
+  RKMI_HD int32_t sstep(int64_t i, int64_t k) const { return s[i * hs + k]; }
+  // checkpoint c of system i (N doubles)
+  RKMI_HD double* ck(int64_t i, int64_t c, int N) const { return ckpt + i * cs + c * N; }
 };
 
 inline TapeView tape_view(const TapeArgs& a, int64_t n, int N) {
@@ -70,7 +82,7 @@ inline TapeView tape_view(const TapeArgs& a, int64_t n, int N) {
   unsigned char* b = static_cast<unsigned char*>(a.tape);
   return TapeView{reinterpret_cast<int32_t*>(b), reinterpret_cast<double*>(b + L.off_h),
                   reinterpret_cast<int32_t*>(b + L.off_s),
-                  reinterpret_cast<double*>(b + L.off_ckpt), n, a.cap, a.K};
+                  reinterpret_cast<double*>(b + L.off_ckpt), n, a.cap, L.hs, L.cs, a.K};
 }
 
 // Forward recorder of system i.
@@ -84,7 +96,7 @@ struct TapeRec {
   template <class V>
   RKMI_HD void checkpoint(int64_t c, const V& y) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) T.ckpt[(c * N + k) * T.n + i] = y[k];
+    for (int k = 0; k < N; ++k) T.ck(i, c, N)[k] = y[k];
   }
   template <class V>
   RKMI_HD void accept(double h, int m, const V& yn, int64_t nstep) {
@@ -93,8 +105,8 @@ struct TapeRec {
       full = true;
       return;
     }
-    T.h[k * T.n + i] = h;
-    T.s[k * T.n + i] = m;
+    T.h[i * T.hs + k] = h;
+    T.s[i * T.hs + k] = m;
     if (++phase == T.K) {          // nstep % K == 0: checkpoint nstep / K
       phase = 0;
       checkpoint(++ck, yn);
@@ -206,7 +218,7 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
     // step-start states of the segment, from its checkpoint
     V y;
 #pragma unroll
-    for (int r = 0; r < N; ++r) y[r] = T.ckpt[(seg * N + r) * n + i];
+    for (int r = 0; r < N; ++r) y[r] = T.ck(i, seg, N)[r];
     for (int64_t k = k0; k < k1; ++k) {
       double* const yk = ys + (k - k0) * N * kLdsStride;
 #pragma unroll
@@ -214,13 +226,13 @@ RKMI_HD int32_t adjoint_system(const typename Prob::Params& prm, int64_t n, int6
       if (k + 1 < k1) {
         V F, yn;
         Prob::rhs(L, prm, y, F);
-        rkc_step<Prob>(L, prm, y, F, T.h[k * n + i], T.s[k * n + i], yn, slot);
+        rkc_step<Prob>(L, prm, y, F, T.hstep(i, k), T.sstep(i, k), yn, slot);
         y = yn;
       }
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {
-      const int sk = T.s[k * n + i];
-      const double hk = T.h[k * n + i];
+      const int sk = T.sstep(i, k);
+      const double hk = T.hstep(i, k);
       if (sk < 2 || sk > max_stages) {
         st = kSysTape;
         break;
@@ -326,7 +338,7 @@ RKMI_HD int32_t adjoint_system_rkck(const typename Prob::Params& prm, int64_t n,
     const int64_t k1 = (k0 + T.K < M) ? k0 + T.K : M;
     V y;
 #pragma unroll
-    for (int r = 0; r < N; ++r) y[r] = T.ckpt[(seg * N + r) * n + i];
+    for (int r = 0; r < N; ++r) y[r] = T.ck(i, seg, N)[r];
     for (int64_t k = k0; k < k1; ++k) {
       double* const yk = ys + (k - k0) * N * kLdsStride;
 #pragma unroll
@@ -334,12 +346,12 @@ RKMI_HD int32_t adjoint_system_rkck(const typename Prob::Params& prm, int64_t n,
       if (k + 1 < k1) {
         V F, yt, ye;
         Prob::rhs(L, prm, y, F);
-        rkck_trial<Prob>(L, prm, y, F, T.h[k * n + i], yt, ye, slot);
+        rkck_trial<Prob>(L, prm, y, F, T.hstep(i, k), yt, ye, slot);
         y = yt;
       }
     }
     for (int64_t k = k1 - 1; k >= k0; --k) {
-      const double hk = T.h[k * n + i];
+      const double hk = T.hstep(i, k);
       const double* const yk = ys + (k - k0) * N * kLdsStride;
 #pragma unroll
       for (int r = 0; r < N; ++r) {

@@ -111,6 +111,52 @@ __device__ double group_chain_sum(const Grp<GP>& x, const double* v) {
   return __shfl(s, kLanes - 1, GP::kL);
 }
 
+// Two such sums in one pass along the chain (the values of u and w in index
+// order, each from +0), both returned to every lane of the group.
+template <class GP, int Nv>
+__device__ void group_chain_sum2(const Grp<GP>& x, const double* u, const double* w, double& su,
+                                 double& sw) {
+  constexpr int kPer = 8, kLanes = (Nv + kPer - 1) / kPer;
+  static_assert(kLanes <= GP::kL && kLanes <= 16, "chain within a row of the group");
+  const int r = x.r;
+  const int off = r < kLanes ? kPer * r : 0;
+  const double2* pu = reinterpret_cast<const double2*>(u + off);
+  const double2* pw = reinterpret_cast<const double2*>(w + off);
+  double a[kPer], b[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer / 2; ++q) {
+    const double2 s = pu[q], t = pw[q];
+    a[2 * q] = s.x;
+    a[2 * q + 1] = s.y;
+    b[2 * q] = t.x;
+    b[2 * q + 1] = t.y;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q)
+    if (kPer * (kLanes - 1) + q >= Nv) {
+      a[q] = (r == kLanes - 1) ? 0.0 : a[q];
+      b[q] = (r == kLanes - 1) ? 0.0 : b[q];
+    }
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int step = 0; step < kLanes; ++step) {
+    double v1 = dpp_row_shr1(s1), v2 = dpp_row_shr1(s2);
+    if (GP::kL < 16) {
+      v1 = r == 0 ? 0.0 : v1;
+      v2 = r == 0 ? 0.0 : v2;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      v1 = v1 + a[q];
+      v2 = v2 + b[q];
+    }
+    s1 = v1;
+    s2 = v2;
+  }
+  su = __shfl(s1, kLanes - 1, GP::kL);
+  sw = __shfl(s2, kLanes - 1, GP::kL);
+}
+
 // sum_k t_k over k = 0..N-1 in order, t_k held by the owners; every lane of
 // the group gets the same value.
 template <class GP>
@@ -167,9 +213,22 @@ struct GroupOwnRhs<GP, std::void_t<decltype(GP::kOwnRhs)>> {
   static constexpr bool value = GP::kOwnRhs;
 };
 
+// A group problem with the energy equation (GP::kThermal: unknowns T, Y).
+template <class GP, class = void>
+struct GroupThermal {
+  static constexpr bool value = false;
+};
+template <class GP>
+struct GroupThermal<GP, std::void_t<decltype(GP::kThermal)>> {
+  static constexpr bool value = GP::kThermal;
+};
+
 template <class GP>
 __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>& x,
                                       const double (&y)[GP::S], double (&f)[GP::S]);
+template <class GP>
+__device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
+                                  const double (&y)[GP::S], double (&f)[GP::S]);
 
 // Right-hand side of the group's system at y (owned slots) into f.
 template <class GP>
@@ -177,6 +236,8 @@ __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const do
                           double (&f)[GP::S]) {
   if constexpr (GroupOwnRhs<GP>::value)
     GP::rhs(L, x, y, f);
+  else if constexpr (GroupThermal<GP>::value)
+    group_rhs_thermal<GP>(L, x, y, f);
   else
     group_rhs_mass_action<GP>(L, x, y, f);
 }
@@ -187,6 +248,11 @@ template <class GP>
 __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>& x,
                                       const double (&y)[GP::S], double (&f)[GP::S]) {
   static_assert(GP::S == 2 && GP::kOffC % 2 == 0, "two species slots per lane, aligned C");
+  static_assert(GP::kOffC + GP::N < GP::kOffQ && GP::kSentinel == GP::R * GP::kL &&
+                    GP::kOffQ + GP::kSentinel < GP::kOffRed &&
+                    GP::kOffRed + GP::N <= GP::kOffQ + GP::kNegOff &&
+                    GP::kOffQ + GP::kNegOff + GP::R * GP::kL <= GP::kLdsPerSystem,
+                "C, +q, the zero, the scratch and -q are disjoint");
   constexpr int N = GP::N, LL = GP::kL;
   double* const C = x.lds + GP::kOffC;
   double* const Q = x.lds + GP::kOffQ;
@@ -252,6 +318,113 @@ __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>&
   }
   f[0] = owns<GP>(x, 0) ? (L.W[0] * om0) * L.irho : 0.0;
   f[1] = owns<GP>(x, 1) ? (L.W[1] * acc) * L.irho : 0.0;
+}
+
+// Mass action with the energy equation (Sec. 4.2 at constant volume): the
+// owner of T writes it beside the concentrations, every lane reads it and
+// forms ln T and 1/T, each position's lane its reaction's rate coefficients
+// k_f = exp(ln A + b ln T - E (1/T)) and k_r = k_f (1/K) (read from the
+// uniform data at every evaluation), the species part as
+// group_rhs_mass_action, then the species owners write (e_k omega_k) W_k and
+// Y_k c_v,k(T) and two chain sums over the species give
+// dT/dt = -((sum * (1/rho)) / c_v): the reference evaluation's operations in
+// its order.
+template <class GP>
+__device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
+                                  const double (&y)[GP::S], double (&f)[GP::S]) {
+  static_assert(GP::S == 2 && GP::kOffC % 2 == 0 && GP::kOffE1 % 2 == 0 && GP::kOffE2 % 2 == 0,
+                "two unknowns per lane, aligned areas");
+  static_assert(sizeof(RkcCoef) <= sizeof(double) * (GP::kOffE1 - GP::kOffRed),
+                "the energy rows leave the RKC coefficients kept in the scratch intact");
+  static_assert(GP::kOffC + GP::NS < GP::kOffT && GP::kOffT < GP::kOffQ &&
+                    GP::kSentinel == GP::R * GP::kL && GP::kOffQ + GP::kSentinel < GP::kOffRed &&
+                    GP::kOffRed + GP::N <= GP::kOffQ + GP::kNegOff &&
+                    GP::kOffE1 + GP::NS <= GP::kOffE2 &&
+                    GP::kOffE2 + GP::NS <= GP::kOffQ + GP::kNegOff &&
+                    GP::kOffQ + GP::kNegOff + GP::R * GP::kL <= GP::kLdsPerSystem,
+                "C, T, +q, the zero, the scratch, the energy rows and -q are disjoint");
+  constexpr int NS = GP::NS, NR = GP::NR, LL = GP::kL;
+  const double* const p = L.prm;
+  double* const C = x.lds + GP::kOffC;
+  double* const Q = x.lds + GP::kOffQ;
+  const int z0 = opaque_zero();
+  const uint32_t* const rxt = GP::kRx + z0 + x.r;
+  const uint32_t* const tct = GP::kTc + z0 + x.r;
+#pragma unroll
+  for (int m = 0; m < GP::S; ++m) {
+    const int u = x.sp[m];
+    if (u == 0) x.lds[GP::kOffT] = y[m];
+    if (u > 0) C[u - 1] = (L.rho * y[m]) * L.iW[m];
+  }
+  group_sync();
+  const double T = x.lds[GP::kOffT];
+  const double lnT = crm::cr_log(T);
+  const double invT = 1.0 / T;
+  const double M = group_chain_sum<GP, NS>(x, C);
+  uint32_t tcw[GP::kTermWords];
+#pragma unroll
+  for (int w = 0; w < GP::kTermWords; ++w) tcw[w] = tct[w * LL];
+#pragma unroll 1
+  for (int m = 0; m < GP::R; ++m) {
+    const int pos = m * LL + x.r;
+    const int j = GP::kRxOf[pos + z0];
+    double kf = 0.0, kr = 0.0;
+    if (j >= 0) {
+      kf = crm::cr_exp(p[j] + p[NR + j] * lnT - p[2 * NR + j] * invT);
+      kr = kf * p[3 * NR + j];
+    }
+    const uint32_t code = rxt[m * LL];
+    const uint32_t ib = (code >> 8) & 0xffu, id = code >> 24;
+    const double ca = C[code & 0xffu], cc = C[(code >> 16) & 0xffu];
+    double cb = C[ib], cd = C[id];
+    if (m >= GP::kMSlot) {
+      cb = ib == (uint32_t)NS ? M : cb;
+      cd = id == (uint32_t)NS ? M : cd;
+    }
+    const double q = (kf * ca) * cb - (kr * cc) * cd;
+    Q[pos] = q;
+    Q[GP::kNegOff + pos] = -q;
+  }
+  group_sync();
+  double acc = 0.0, om0 = 0.0;
+#pragma unroll
+  for (int t = 0; t < GP::kTermLen; ++t) {
+    uint32_t word = tcw[t / GP::kTermsPerWord];
+    opaque(word);
+    const uint32_t code = (word >> ((t % GP::kTermsPerWord) * GP::kTermBits)) &
+                          ((1u << GP::kTermBits) - 1u);
+    acc = acc + Q[code];
+    if (t % GP::kChunk == GP::kChunk - 1 && ((GP::kSwitchChunks >> (t / GP::kChunk)) & 1)) {
+      const bool sw = t / GP::kChunk + 1 == L.bnd;
+      om0 = sw ? acc : om0;
+      acc = sw ? 0.0 : acc;
+    }
+    if (t % 4 == 3) {
+      opaque_f64(acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const double om[2] = {om0, acc};
+  // the energy sums' terms, species by species
+  double* const R1 = x.lds + GP::kOffE1;
+  double* const R2 = x.lds + GP::kOffE2;
+#pragma unroll
+  for (int m = 0; m < GP::S; ++m) {
+    const int u = x.sp[m];
+    f[m] = u > 0 ? (L.W[m] * om[m]) * L.irho : 0.0;
+    if (u > 0) {
+      const double e = L.u0[m] + (L.cv0[m] + L.cv1[m] * T) * T;
+      R1[u - 1] = (e * om[m]) * L.W[m];
+      R2[u - 1] = y[m] * (L.cv0[m] + 2.0 * L.cv1[m] * T);
+    }
+  }
+  group_sync();
+  double sum, cv;
+  group_chain_sum2<GP, NS>(x, R1, R2, sum, cv);
+  group_sync();
+#pragma unroll
+  for (int m = 0; m < GP::S; ++m)
+    if (x.sp[m] == 0) f[m] = -((sum * L.irho) / cv);
 }
 
 template <class GP>
@@ -956,6 +1129,19 @@ int launch_with_group(const LaunchArgs* a, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (a->schedule == kSchedPlain || a->schedule == kSchedPersistent) return launch<Prob>(a, stream);
   if (!a->ws || a->ws_bytes < kQueueBytes) return launch<Prob>(a, stream);   // no queue: plain
+  if (a->pilot)
+    return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck, true>(a, s)
+                                    : launch_group_method<GP, kMethodRkc, true>(a, s);
+  return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck, false>(a, s)
+                                  : launch_group_method<GP, kMethodRkc, false>(a, s);
+}
+
+// Launches the group kernels of GP under every schedule (problems without
+// one-lane kernels).
+template <class GP>
+int launch_group_only(const LaunchArgs* a, void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (a->n > 0 && (!a->ws || a->ws_bytes < kQueueBytes)) return kLaunchWorkspace;
   if (a->pilot)
     return a->method == kMethodRkck ? launch_group_method<GP, kMethodRkck, true>(a, s)
                                     : launch_group_method<GP, kMethodRkc, true>(a, s);

@@ -279,6 +279,11 @@ WORKLOADS = {
     "net13_thermal_rkc": Workload("net13_thermal_rkc", "rkc", "net13_thermal", 1 << 18, 0.0,
                                   1e-5, 1e-8, 1e-12, 8008, (1000.0, 2500.0),
                                   launch=dict(schedule=1, cost_order=1), global_steps=10),
+    # the largest compiled network with the energy equation (53 species + T, the
+    # size of Sec. 4.2's mechanism), one global step of 1e-6 s on the group kernels
+    "net53_thermal_rkc": Workload("net53_thermal_rkc", "rkc", "net53_thermal", 1 << 18, 0.0,
+                                  1e-6, 1e-8, 1e-12, 8053, (1000.0, 2500.0),
+                                  launch=dict(schedule=3)),
     "net13_adjoint": Workload("net13_adjoint", "rkc", "net13", 1 << 16, 0.0, 1e-6, 1e-8, 1e-12,
                               5005, (1000.0, 2500.0)),
     "net13_adjoint_rkck": Workload("net13_adjoint_rkck", "rkck", "net13", 1 << 16, 0.0, 1e-6,

@@ -506,10 +506,15 @@ def test_carried_state_equals_oracle(rk, orc, problem, method, n, dt, k, schedul
 
 @pytest.mark.parametrize("n_sp,method,n,t1,schedule,cost_order", [
     (13, "rkc", 4133, 1e-6, 1, 0), (13, "rkc", 4133, 1e-6, 2, 1), (9, "rkc", 2000, 1e-6, 2, 0),
-    (13, "rkck", 700, 5e-8, 1, 1)])
+    (13, "rkck", 700, 5e-8, 1, 1),
+    # 32 and 53 species + T: the group kernels (32 lanes per system) under every
+    # schedule, the last group of a wave partly filled (odd n)
+    (32, "rkc", 67, 1e-8, 3, 0), (32, "rkck", 97, 1e-8, 1, 1), (53, "rkc", 37, 1e-8, 3, 1),
+    (53, "rkc", 33, 5e-9, 2, 0), (53, "rkck", 67, 1e-8, 3, 0)])
 def test_thermal_networks(rk, orc, n_sp, method, n, t1, schedule, cost_order):
     """Networks with the energy equation (state T, Y; rate coefficients at the
-    current T): every schedule equals the oracle."""
+    current T): every schedule equals the oracle; up to 15 species on the
+    one-lane kernels, above on the group kernels whatever the schedule."""
     say(f"case thermal net{n_sp} {method} n={n} schedule={schedule} cost={cost_order}")
     net = I.thermal_network(n_sp)
     y0, g = I.thermal_inputs(net, n, 8100 + n_sp, (1000.0, 2500.0))
@@ -520,14 +525,16 @@ def test_thermal_networks(rk, orc, n_sp, method, n, t1, schedule, cost_order):
     compare(yg, sg, stg, yo, so, sto, 1e-12, f"thermal net{n_sp} {method}")
 
 
-def test_thermal_full_size_sampled(rk, orc):
-    """The 2^18-system 13-species workload with the energy equation in the
-    benchmark's launch, ten global steps of 1e-6 s; the oracle recomputes a
-    spread sample of 128 systems."""
+@pytest.mark.parametrize("wname,n_sample", [("net13_thermal_rkc", 128),
+                                           ("net53_thermal_rkc", 16)])
+def test_thermal_full_size_sampled(rk, orc, wname, n_sample):
+    """The 2^18-system workloads with the energy equation in the benchmark's
+    launch: 13 species over ten global steps of 1e-6 s (one-lane kernels), 53
+    species over one (group kernels); the oracle recomputes a spread sample."""
     import torch
-    w = I.WORKLOADS["net13_thermal_rkc"]
+    w = I.WORKLOADS[wname]
     say(f"case full-size {w.name} n={w.n}")
-    net = I.thermal_network(13)
+    net = I.thermal_network(int(w.problem[3:-8]))
     y0, g = I.workload_inputs(w)
     prob, pb = rk.Problem.network_thermal(net), orc.network_thermal(net)
     yd, gd = torch.from_numpy(y0).cuda(), torch.from_numpy(g).cuda()
@@ -537,10 +544,11 @@ def test_thermal_full_size_sampled(rk, orc):
                                          w.atol, out=yd, **w.launch)
     torch.cuda.synchronize()
     yg, sg, stg = yd.cpu().numpy(), st.cpu().numpy(), stats.cpu().numpy()
-    idx = np.unique(np.linspace(0, w.n - 1, 128).astype(np.int64))
+    idx = np.unique(np.linspace(0, w.n - 1, n_sample).astype(np.int64))
     yo = np.ascontiguousarray(y0[:, idx])
     gs = np.ascontiguousarray(g[:, idx])
     for k in range(w.global_steps):
         yo, so, sto = orc.rkc_batch(pb, yo, gs, w.t0 + k * dt, w.t0 + (k + 1) * dt, w.rtol, w.atol)
-    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, "full thermal sample")
+    compare(yg[:, idx], sg[idx], stg[:, idx], yo, so, sto, w.atol, f"full {w.name} sample")
     assert np.all(sg == 0)
+    assert np.abs(yg[1:].sum(0) - 1.0).max() < 1e-11
