@@ -461,6 +461,9 @@ def main():
                          "-1: the workload's own choice")
     ap.add_argument("--refill", type=int, default=0,
                     help="persistent schedule: idle lanes that trigger a refill (0: default)")
+    ap.add_argument("--group-align", type=int, default=0,
+                    help="group schedule: evaluations a group at its error estimate waits for "
+                         "another group of its wave (0: the library default, < 0: never)")
     ap.add_argument("--sr-method", default="power", choices=("power", "gershgorin"),
                     help="RKC spectral radius: the nonlinear power method or the Gershgorin "
                          "bound of the analytic Jacobian (van der Pol, networks up to 16 species)")
@@ -543,6 +546,8 @@ def main():
                 launch["sr_method"] = args.sr_method
             if args.refill:
                 launch["refill"] = args.refill
+            if args.group_align:
+                launch["group_align"] = args.group_align
             self.launch = launch
             name = sched_names[launch.get("schedule", 0)]
             if launch.get("cost_order"):

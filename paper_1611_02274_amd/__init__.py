@@ -114,11 +114,13 @@ SR_METHODS = {"power": 0, "gershgorin": 1}
 
 
 def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refill=None,
-             cost_order=None, sr_method=None):
+             cost_order=None, sr_method=None, group_align=None):
     """rk_options; sr_method (RKC spectral radius): "power" (the nonlinear power
-    method, default) or "gershgorin" (the bound of the analytic Jacobian)."""
+    method, default) or "gershgorin" (the bound of the analytic Jacobian);
+    group_align (group schedule): evaluations a group at its error estimate
+    waits for another group of its wave (0 default, negative never)."""
     if all(v is None for v in (max_steps, sr_period, sr_itmax, schedule, refill, cost_order,
-                               sr_method)):
+                               sr_method, group_align)):
         return None
     o = _lib.Options()
     o.max_steps = int(max_steps or 0)
@@ -128,6 +130,7 @@ def _options(max_steps=None, sr_period=None, sr_itmax=None, schedule=None, refil
     o.refill = int(refill or 0)
     o.cost_order = int(bool(cost_order))
     o.sr_method = SR_METHODS[sr_method] if isinstance(sr_method, str) else int(sr_method or 0)
+    o.group_align = int(group_align or 0)
     return o
 
 

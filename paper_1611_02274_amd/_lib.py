@@ -36,7 +36,8 @@ class MechDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("sr_period", C.c_int32), ("sr_itmax", C.c_int32),
                 ("schedule", C.c_int32), ("refill", C.c_int32), ("cost_order", C.c_int32),
-                ("sr_method", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("sr_method", C.c_int32), ("group_align", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class BatchSchedule(C.Structure):

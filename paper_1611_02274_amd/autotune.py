@@ -1,7 +1,8 @@
 """Schedule autotuner for batched integration.
 
 Picks, by timing candidates on a seeded sample of the workload, the schedule
-of one network (plain / persistent / group, refill threshold) or of a ragged
+of one network (plain / persistent / group, refill threshold, cost order,
+group alignment) or of a ragged
 batch (network order, per-network refill thresholds, workgroups per compute
 unit).  Results are cached per (network topologies, method, rtol, device) in a
 JSON file, so a workload is tuned once per machine.  Every candidate computes
@@ -79,6 +80,9 @@ NETWORK_CANDIDATES = (
     dict(schedule=1),                                   # plain, one lane per system
     dict(schedule=2, refill=8), dict(schedule=2, refill=16), dict(schedule=2, refill=32),
     dict(schedule=3, refill=16), dict(schedule=3, refill=32),   # group (large networks)
+    # group: how long a group at its error estimate waits for the other groups
+    # of its wave (never; longer than the default)
+    dict(schedule=3, refill=32, group_align=-1), dict(schedule=3, refill=32, group_align=8),
     # systems handed out in decreasing cost (a loose-tolerance pilot ranks them)
     dict(schedule=1, cost_order=1), dict(schedule=2, refill=16, cost_order=1),
 )
@@ -87,7 +91,8 @@ NETWORK_CANDIDATES = (
 def tune_network(problem, method: str, y0, g, t0, t1, rtol, atol, fraction=0.05,
                  minimum=16384, seed=0, force=False) -> dict:
     """Best schedule for integrating this network: returns the keyword
-    arguments for integrate_rkck / integrate_rkc (schedule, refill)."""
+    arguments for integrate_rkck / integrate_rkc (schedule, refill, cost order,
+    group alignment)."""
     import torch
 
     from . import integrate_rkc, integrate_rkck

@@ -151,6 +151,7 @@ void fill_ctl(rkmi::Ctl& c, double t0, double t1, double rtol, double atol,
   c.refill = (opt && opt->refill > 0) ? (opt->refill > rkmi::kLdsStride ? rkmi::kLdsStride
                                                                         : opt->refill)
                                       : rkmi::kDefaultRefill;
+  c.align = opt ? (opt->group_align > 64 ? 64 : opt->group_align) : 0;
 }
 
 // Launch arguments and the launch-uniform controls of the drivers.
@@ -192,7 +193,7 @@ int integrate(int method, rk_problem p, int64_t n, const double* y0, double* y1,
   if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(RK_EINVAL, "rtol must be positive");
   if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(RK_EINVAL, "atol must be >= 0");
   if (opt) {
-    for (int k = 0; k < 4; ++k)
+    for (size_t k = 0; k < sizeof(opt->reserved) / sizeof(opt->reserved[0]); ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->schedule < rkmi::kSchedAuto || opt->schedule > rkmi::kSchedGroup)
       return fail(RK_EUNSUPPORTED, "schedule %d is not available", opt->schedule);
@@ -845,7 +846,7 @@ int rk_batch_integrate_rkc(rk_batch b, const int64_t* n_sys, double* const* y,
   if (!b) return fail(RK_EINVAL, "batch handle is NULL");
   if (!n_sys || !y || !g) return fail(RK_EINVAL, "n_sys, y and g are required");
   if (opt) {
-    for (int k = 0; k < 4; ++k)
+    for (size_t k = 0; k < sizeof(opt->reserved) / sizeof(opt->reserved[0]); ++k)
       if (opt->reserved[k]) return fail(RK_EINVAL, "rk_options.reserved must be zero");
     if (opt->cost_order)
       return fail(RK_EUNSUPPORTED, "cost_order is not available for a batch");

@@ -587,6 +587,11 @@ struct GRkck {
     return next_attempt(x, c);
   }
 
+  // The next advance runs the error estimate and the controller.
+  __device__ bool at_error() const { return stage == 6; }
+  // Evaluations before that (0 when there already).
+  __device__ int to_error() const { return 6 - stage; }
+
   __device__ void stats(int32_t (&st)[kNStats]) const {
     st[kStAccept] = n_acc;
     st[kStReject] = n_rej;
@@ -900,6 +905,11 @@ struct GRkc {
     return next_attempt(x, c);
   }
 
+  // The next advance runs the error estimate and the controller.
+  __device__ bool at_error() const { return phase == kPhError; }
+  // Evaluations before that while in the stages (else 0).
+  __device__ int to_error() const { return phase == kPhStage ? st_m - st_j + 1 : 0; }
+
   __device__ void stats(int32_t (&st)[kNStats]) const {
     st[kStAccept] = n_acc;
     st[kStReject] = n_rej;
@@ -974,6 +984,8 @@ struct GDriver {
   __device__ bool advance(const Ctl& c, const Grp<GP>& x, const double (&f)[GP::S]) {
     return D.advance(x, c, f);
   }
+  __device__ bool at_error() const { return D.at_error(); }
+  __device__ int to_error() const { return D.to_error(); }
   __device__ void finish(int64_t n, int64_t i, double* y1, int32_t* status, int32_t* stats,
                          const Grp<GP>& x, double* carry = nullptr) const {
     const auto& y = D.state();
@@ -1021,6 +1033,12 @@ constexpr int group_lds_doubles() {
   return kGroups<GP> * GP::kLdsPerSystem;
 }
 
+// Default of Ctl::align per method: on the 53-species network at 2^16 systems
+// the RKC kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5,
+// the RKCK kernel 1111 / 1096 / 1081 / 1089 ms with none / 1 / 5 / 8.
+template <int Method>
+constexpr int kGroupAlignDefault = Method == kMethodRkck ? 5 : 1;
+
 // Persistent loop at group granularity: as persistent_loop, with a group of
 // kL lanes as the unit that takes a system and one right-hand-side
 // evaluation as the unit of progress; the refill threshold counts lanes.
@@ -1035,6 +1053,7 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
   GDriver<GP, Method> D;
   int64_t i = -1;
   bool active = false, retired = false;
+  const int align = c.align > 0 ? c.align : (c.align == 0 ? kGroupAlignDefault<Method> : 0);
   for (;;) {
     const bool idle = !active && !retired;
     const unsigned long long idle_mask = __ballot(idle);
@@ -1061,7 +1080,18 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
       }
     }
     if (!__ballot(!retired)) break;
-    if (active) {
+    // Phase alignment: the groups of a wave evaluate together, but the code
+    // that follows an evaluation depends on each group's phase, and groups in
+    // different phases run their codes one after the other.  A group whose
+    // next step is the error estimate and the controller (the longest of
+    // them) waits while another group is at most `align` evaluations from
+    // its own, so that both run it together; its arithmetic is unchanged.
+    bool run = active;
+    if (align > 0) {
+      const int te = active ? D.to_error() : 0;
+      if (__ballot(te > 0 && te <= align) && active && D.at_error()) run = false;
+    }
+    if (run) {
       double f[GP::S];
       group_rhs<GP>(D.D.L, x, D.arg(), f);
       if (!D.advance(c, x, f)) {

@@ -25,6 +25,8 @@ struct Ctl {
   int sr_itmax;       // power-method iterations (50)
   int sr_method;      // kSrPower | kSrGershgorin
   int refill;         // persistent schedule: idle lanes that trigger a refill (1..64)
+  int align;          // group schedule: a group at its error phase waits while another
+                      // group of the wave is 1..align evaluations from its own (0: never)
 };
 
 // Arguments of one integration launch (device pointers, launch-uniform controls).

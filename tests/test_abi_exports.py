@@ -77,5 +77,6 @@ def test_cost_order_workspace_host_only():
         o = rk._options(schedule=1, cost_order=1)
         want = a256(6 * 4 * n) + a256(4 * n) + 2 * a256(4096 * 4)
         assert L.rk_workspace_bytes(p.handle, _lib.RK_METHOD_RKC, n, C.byref(o)) == want
-    # max_steps, four int32 fields, cost_order, sr_method, reserved[4]: the struct keeps its size
+    # max_steps, four int32 fields, cost_order, sr_method, group_align, reserved[3]: the
+    # struct keeps its size
     assert C.sizeof(_lib.Options) == 8 + 4 * 4 + 4 + 4 * 5 == 48

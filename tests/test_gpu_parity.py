@@ -273,7 +273,8 @@ def test_device_math_equals_host_and_oracle(rk, orc):
 def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
     """The plain, the persistent (queue-refilled) and the group (16 lanes per
     system, for the 32- and 53-species networks) schedules, each with and
-    without the cost order, give identical bits, and all equal the oracle."""
+    without the cost order, give identical bits (the group one also with every
+    phase alignment), and all equal the oracle."""
     import torch
     say(f"case schedules {problem} {method} n={n}")
     if problem == "vdp":
@@ -285,6 +286,10 @@ def test_schedules_agree_bitwise(rk, orc, problem, method, n, t1, T_range):
         prob, pb, atol = rk.Problem.network(net), orc.network(net), 1e-12
     res = [_gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, atol, schedule=s, cost_order=co)
            for co in (0, 1) for s in (1, 2, 3)]
+    if problem in ("net32", "net53"):
+        # the group schedule with no phase alignment and a long one
+        res += [_gpu(rk, method, prob, y0, g, 0.0, t1, 1e-8, atol, schedule=3, group_align=a)
+                for a in (-1, 8)]
     for other in res[1:]:
         for a, b in zip(res[0], other):
             assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
