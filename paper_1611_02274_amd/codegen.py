@@ -470,11 +470,12 @@ def _species_terms(net):
     return terms
 
 
-def _table(name, ctype, values, per_line=16):
+def _table(name, ctype, values, per_line=16, align=0):
     rows = [", ".join(str(v) for v in values[i:i + per_line])
             for i in range(0, len(values), per_line)]
     body = ",\n      ".join(rows)
-    return f"  static constexpr {ctype} {name}[{len(values)}] = {{\n      {body}}};"
+    al = f"alignas({align}) " if align else ""
+    return f"  {al}static constexpr {ctype} {name}[{len(values)}] = {{\n      {body}}};"
 
 
 # Group variants: a lane's species list is consumed in chunks of this many
@@ -611,11 +612,28 @@ def _group_layout(net, L, thermal=False):
                 switch=sum(1 << (b - 1) for b in set(bnd) if b > 0))
 
 
+def _lane_major(words, L, per_lane):
+    """A [per_lane][L] table (entry w of lane r at w L + r) as [L][per_lane']
+    with per_lane' = per_lane rounded up to whole 16-byte vectors (zeros)."""
+    padded = -(-per_lane // 4) * 4
+    out = [0] * (L * padded)
+    for r in range(L):
+        for w in range(per_lane):
+            out[r * padded + w] = words[w * L + r]
+    return out, padded
+
+
 def _group_tables(G) -> str:
+    rx, rx_words = _lane_major(G["rx"], G["L"], G["R"])
+    tc, tc_words = _lane_major(G["tc"], G["L"], G["n_words"])
     return f"""{_table("kSp", "int", G["sp"])}
 {_table("kRxOf", "int16_t", G["rx_of"])}
-{_table("kRx", "uint32_t", G["rx"])}
-{_table("kTc", "uint32_t", G["tc"])}
+  // lane r's operand codes and packed term codes, each lane's contiguous and
+  // 16-byte aligned (read as whole vectors at every evaluation)
+  static constexpr int kRxWords = {rx_words};
+  static constexpr int kTcWords = {tc_words};
+{_table("kRx", "uint32_t", rx, align=16)}
+{_table("kTc", "uint32_t", tc, align=16)}
 {_table("kBnd", "int", G["bnd"])}
   // chunks at whose end some lane moves its accumulator to slot 0 (bit c)
   static constexpr uint64_t kSwitchChunks = {G["switch"]}ull;"""
@@ -668,8 +686,6 @@ struct GNet {{
 {_group_tables(G)}
   struct Lane {{
     double kf[R], kr[R];
-    uint32_t rx[R];
-    uint32_t tc[kTermWords];
     double W[S], iW[S];
     double rho, irho;
     int bnd;   // chunks of the slot-0 list
@@ -697,10 +713,7 @@ struct GNet {{
       const int j = kRxOf[m * kL + x.r];
       L.kf[m] = j >= 0 ? Q[m * kL + x.r] : 0.0;
       L.kr[m] = j >= 0 ? L.kf[m] * p[3 * NR + j] : 0.0;
-      L.rx[m] = kRx[m * kL + x.r];
     }}
-#pragma unroll
-    for (int w = 0; w < kTermWords; ++w) L.tc[w] = kTc[w * kL + x.r];
 #pragma unroll
     for (int m = 0; m < S; ++m) {{
       const int k = x.sp[m];

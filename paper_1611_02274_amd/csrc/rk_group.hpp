@@ -24,7 +24,8 @@
 // kLdsPerSystem: +q at kOffQ + p, the zero at kOffQ + kSentinel, -q at
 // kOffQ + kNegOff + p), the tables kSp (species of slot m of lane r at
 // m L + r, -1 for none), kRx (packed operand species of each position's
-// reaction, [M] as index N), kTc (each lane's signed rate positions, packed:
+// reaction, [M] as index N; lane-major, kRxWords per lane), kTc (each lane's
+// signed rate positions, packed, lane-major, kTcWords per lane:
 // its slot-0 species' list padded with the zero to whole chunks of kChunk
 // terms, then its slot-1 species' list, kTermLen in all), kBnd (the chunks
 // of the slot-0 list) and kSwitchChunks (the chunks at whose end some lane
@@ -242,6 +243,22 @@ __device__ void group_rhs(const typename GP::Lane& L, const Grp<GP>& x, const do
     group_rhs_mass_action<GP>(L, x, y, f);
 }
 
+// Lane r's row of a lane-major code table (Words 32-bit words, a multiple of
+// four, 16-byte aligned) as whole-vector loads.
+template <int Words>
+__device__ inline void load_row(const uint32_t* table, int row, uint32_t (&w)[Words]) {
+  static_assert(Words % 4 == 0, "rows of whole 16-byte vectors");
+  const uint4* const v = reinterpret_cast<const uint4*>(table) + row * (Words / 4);
+#pragma unroll
+  for (int q = 0; q < Words / 4; ++q) {
+    const uint4 u = v[q];
+    w[4 * q] = u.x;
+    w[4 * q + 1] = u.y;
+    w[4 * q + 2] = u.z;
+    w[4 * q + 3] = u.w;
+  }
+}
+
 // Mass action: concentrations, [M] and rates of progress exchanged through
 // the group's LDS area (the scheme in the header comment).
 template <class GP>
@@ -259,20 +276,16 @@ __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>&
   // the operand and term tables are read from constant memory at each
   // evaluation (vector loads, cached, issued here so that the exchanges below
   // cover their latency), not held in registers across the integration
-  const int z0 = opaque_zero();
-  const uint32_t* const rxt = GP::kRx + z0 + x.r;
-  const uint32_t* const tct = GP::kTc + z0 + x.r;
-  uint32_t rxw[GP::R];
-#pragma unroll
-  for (int m = 0; m < GP::R; ++m) rxw[m] = rxt[m * LL];
+  const int row = opaque_zero() + x.r;
+  uint32_t rxw[GP::kRxWords];
+  load_row<GP::kRxWords>(GP::kRx, row, rxw);
 #pragma unroll
   for (int m = 0; m < GP::S; ++m)
     if (owns<GP>(x, m)) C[x.sp[m]] = (L.rho * y[m]) * L.iW[m];
   group_sync();
   const double M = group_chain_sum<GP, N>(x, C);
-  uint32_t tcw[GP::kTermWords];
-#pragma unroll
-  for (int w = 0; w < GP::kTermWords; ++w) tcw[w] = tct[w * LL];
+  uint32_t tcw[GP::kTcWords];
+  load_row<GP::kTcWords>(GP::kTc, row, tcw);
 #pragma unroll
   for (int m = 0; m < GP::R; ++m) {
     const int p = m * LL + x.r;
@@ -348,8 +361,7 @@ __device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
   double* const C = x.lds + GP::kOffC;
   double* const Q = x.lds + GP::kOffQ;
   const int z0 = opaque_zero();
-  const uint32_t* const rxt = GP::kRx + z0 + x.r;
-  const uint32_t* const tct = GP::kTc + z0 + x.r;
+  const uint32_t* const rxl = GP::kRx + (z0 + x.r) * GP::kRxWords;
 #pragma unroll
   for (int m = 0; m < GP::S; ++m) {
     const int u = x.sp[m];
@@ -361,9 +373,8 @@ __device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
   const double lnT = crm::cr_log(T);
   const double invT = 1.0 / T;
   const double M = group_chain_sum<GP, NS>(x, C);
-  uint32_t tcw[GP::kTermWords];
-#pragma unroll
-  for (int w = 0; w < GP::kTermWords; ++w) tcw[w] = tct[w * LL];
+  uint32_t tcw[GP::kTcWords];
+  load_row<GP::kTcWords>(GP::kTc, z0 + x.r, tcw);
 #pragma unroll 1
   for (int m = 0; m < GP::R; ++m) {
     const int pos = m * LL + x.r;
@@ -373,7 +384,7 @@ __device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
       kf = crm::cr_exp(p[j] + p[NR + j] * lnT - p[2 * NR + j] * invT);
       kr = kf * p[3 * NR + j];
     }
-    const uint32_t code = rxt[m * LL];
+    const uint32_t code = rxl[m];
     const uint32_t ib = (code >> 8) & 0xffu, id = code >> 24;
     const double ca = C[code & 0xffu], cc = C[(code >> 16) & 0xffu];
     double cb = C[ib], cd = C[id];
