@@ -375,7 +375,9 @@ __device__ void group_rhs_thermal(const typename GP::Lane& L, const Grp<GP>& x,
   const double M = group_chain_sum<GP, NS>(x, C);
   uint32_t tcw[GP::kTcWords];
   load_row<GP::kTcWords>(GP::kTc, z0 + x.r, tcw);
-#pragma unroll 1
+  // two slots per iteration: their exponentials' table reads overlap (2.3 %
+  // over a rolled loop at 53 species)
+#pragma unroll 2
   for (int m = 0; m < GP::R; ++m) {
     const int pos = m * LL + x.r;
     const int j = GP::kRxOf[pos + z0];
