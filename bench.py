@@ -471,7 +471,7 @@ def main():
                     help="run only a device-to-device copy of 1 GiB, three times (the known "
                          "traffic that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
-    big = args.workload.startswith("net53") or args.workload == "ragged"
+    big = args.workload.startswith(("net53", "net32")) or args.workload == "ragged"
     if args.steps is None:
         args.steps = (1 if args.workload == "ragged" else 2) if big else 10
     if args.warmup is None:

@@ -272,6 +272,11 @@ WORKLOADS = {
                           (900.0, 2800.0)),
     "net53_rkck": Workload("net53_rkck", "rkck", "net53", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3003,
                            (900.0, 2800.0)),
+    # the 32-species network at the same size (group kernels, 16 lanes per system)
+    "net32_rkc": Workload("net32_rkc", "rkc", "net32", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3203,
+                          (900.0, 2800.0)),
+    "net32_rkck": Workload("net32_rkck", "rkck", "net32", 1 << 20, 0.0, 1e-6, 1e-8, 1e-12, 3203,
+                           (900.0, 2800.0)),
     # ten global steps of 0.1 over [0, 1], each a restart (Sec. 4.1); eps = 1e-10
     "pleiades_rkck": Workload("pleiades_rkck", "rkck", "pleiades", 1 << 18, 0.0, 1.0, 1e-10, 0.0,
                               6006, launch=dict(schedule=3), global_steps=10),
