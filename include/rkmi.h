@@ -113,7 +113,8 @@ typedef struct {
                            controller waits while another group of its wave is at most this
                            many evaluations from its own, so that the wave runs that code
                            once for both (results are unchanged); 0: the default (RKCK 5,
-                           RKC 1), < 0: never wait */
+                           RKC 1; no waiting with the energy equation), < 0: never
+                           wait */
   int32_t reserved[3];  /* set to 0 */
 } rk_options;
 

@@ -1046,11 +1046,17 @@ constexpr int group_lds_doubles() {
   return kGroups<GP> * GP::kLdsPerSystem;
 }
 
-// Default of Ctl::align per method: on the 53-species network at 2^16 systems
-// the RKC kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5,
-// the RKCK kernel 1111 / 1096 / 1081 / 1089 ms with none / 1 / 5 / 8.
-template <int Method>
-constexpr int kGroupAlignDefault = Method == kMethodRkck ? 5 : 1;
+// Default of Ctl::align: on the 53-species network at 2^16 systems the RKC
+// kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5, the RKCK
+// kernel 1111 / 1096 / 1081 / 1089 ms with none / 1 / 5 / 8 (32 species, four
+// groups per wave: RKC 505 / 472 / 525 / 590 ms with none / 1 / 3 / 8).  With
+// the energy equation the evaluation (an exponential per reaction) outweighs
+// the controller, and waiting costs more than it saves (53 species + T at
+// 2^18 systems: 8.54 s without, 8.71 s with 1).
+template <class GP, int Method>
+constexpr int group_align_default() {
+  return GroupThermal<GP>::value ? 0 : (Method == kMethodRkck ? 5 : 1);
+}
 
 // Persistent loop at group granularity: as persistent_loop, with a group of
 // kL lanes as the unit that takes a system and one right-hand-side
@@ -1066,7 +1072,7 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
   GDriver<GP, Method> D;
   int64_t i = -1;
   bool active = false, retired = false;
-  const int align = c.align > 0 ? c.align : (c.align == 0 ? kGroupAlignDefault<Method> : 0);
+  const int align = c.align > 0 ? c.align : (c.align == 0 ? group_align_default<GP, Method>() : 0);
   for (;;) {
     const bool idle = !active && !retired;
     const unsigned long long idle_mask = __ballot(idle);
