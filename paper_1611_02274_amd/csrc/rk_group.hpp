@@ -84,32 +84,43 @@ __device__ inline double dpp_row_shr1(double v) {
 // before it), so each addition is the one of the serial loop.  Adding +0 for
 // the slots past n changes nothing: a sum that starts at +0 is never -0.  The
 // chain stays within one row of 16 lanes (a group starts at a multiple of kL).
+// The same chain one lane step at a time (step() kLanes times, then
+// result()), so that independent work can be placed between the steps.
 template <class GP, int Nv>
-__device__ double group_chain_sum(const Grp<GP>& x, const double* v) {
-  constexpr int kPer = 8, kLanes = (Nv + kPer - 1) / kPer;
+struct ChainSum {
+  static constexpr int kPer = 8, kLanes = (Nv + kPer - 1) / kPer;
   static_assert(kLanes <= GP::kL && kLanes <= 16, "chain within a row of the group");
-  const int r = x.r;
-  const double2* p = reinterpret_cast<const double2*>(v + (r < kLanes ? kPer * r : 0));
   double a[kPer];
+  double s;
+  int r;
+  __device__ ChainSum(const Grp<GP>& x, const double* v) : s(0.0), r(x.r) {
+    const double2* p = reinterpret_cast<const double2*>(v + (r < kLanes ? kPer * r : 0));
 #pragma unroll
-  for (int q = 0; q < kPer / 2; ++q) {
-    const double2 u = p[q];
-    a[2 * q] = u.x;
-    a[2 * q + 1] = u.y;
+    for (int q = 0; q < kPer / 2; ++q) {
+      const double2 u = p[q];
+      a[2 * q] = u.x;
+      a[2 * q + 1] = u.y;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (kPer * (kLanes - 1) + q >= Nv) a[q] = (r == kLanes - 1) ? 0.0 : a[q];
   }
-#pragma unroll
-  for (int q = 0; q < kPer; ++q)
-    if (kPer * (kLanes - 1) + q >= Nv) a[q] = (r == kLanes - 1) ? 0.0 : a[q];
-  double s = 0.0;
-#pragma unroll
-  for (int step = 0; step < kLanes; ++step) {
+  __device__ void step() {
     double u = dpp_row_shr1(s);
     if (GP::kL < 16) u = r == 0 ? 0.0 : u;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) u = u + a[q];
     s = u;
   }
-  return __shfl(s, kLanes - 1, GP::kL);
+  __device__ double result() const { return __shfl(s, kLanes - 1, GP::kL); }
+};
+
+template <class GP, int Nv>
+__device__ double group_chain_sum(const Grp<GP>& x, const double* v) {
+  ChainSum<GP, Nv> ch(x, v);
+#pragma unroll
+  for (int step = 0; step < ChainSum<GP, Nv>::kLanes; ++step) ch.step();
+  return ch.result();
 }
 
 // Two such sums in one pass along the chain (the values of u and w in index
@@ -283,11 +294,21 @@ __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>&
   for (int m = 0; m < GP::S; ++m)
     if (owns<GP>(x, m)) C[x.sp[m]] = (L.rho * y[m]) * L.iW[m];
   group_sync();
-  const double M = group_chain_sum<GP, N>(x, C);
+  // [M] by the chain of lanes, its steps interleaved with the rates of the
+  // slots before the first one that needs [M] (they hide the chain's
+  // dependent additions)
+  ChainSum<GP, N> chain(x, C);
+  constexpr int kChainSteps = ChainSum<GP, N>::kLanes;
+  static_assert(kChainSteps <= GP::kMSlot || GP::kMSlot == GP::R, "[M] formed before its slots");
+  double M = 0.0;
   uint32_t tcw[GP::kTcWords];
-  load_row<GP::kTcWords>(GP::kTc, row, tcw);
 #pragma unroll
   for (int m = 0; m < GP::R; ++m) {
+    if (m < kChainSteps) chain.step();
+    if (m == kChainSteps - 1) {
+      M = chain.result();
+      load_row<GP::kTcWords>(GP::kTc, row, tcw);
+    }
     const int p = m * LL + x.r;
     const uint32_t code = rxw[m];
     const uint32_t ib = (code >> 8) & 0xffu, id = code >> 24;
