@@ -343,9 +343,9 @@ __device__ void group_rhs_mass_action(const typename GP::Lane& L, const Grp<GP>&
       om0 = sw ? acc : om0;
       acc = sw ? 0.0 : acc;
     }
-    if (t % 4 == 3) {
-      // keep the additions next to their loads (else all loads are issued
-      // first and held in registers)
+    if (t % 16 == 15) {
+      // keep the additions near their loads (else all loads are issued first
+      // and held in registers; sixteen in flight: 6 % over four)
       opaque_f64(acc);
       __builtin_amdgcn_sched_barrier(0);
     }
