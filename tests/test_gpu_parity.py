@@ -195,6 +195,15 @@ def test_argument_errors(rk):
     assert f(None, 8, y.data_ptr(), y.data_ptr(), g.data_ptr(), 0.0, 1.0, 1e-6, 0.0, None, None,
              None, 0, None, None) == _lib.RK_EINVAL
     assert call() == _lib.RK_OK
+    # options: a group alignment is accepted (it only concerns group launches);
+    # a nonzero reserved word is refused
+    o = rk._options(schedule=1, group_align=3)
+    assert f(prob.handle, 8, y.data_ptr(), y.data_ptr(), g.data_ptr(), 0.0, 1.0, 1e-6, 0.0, None,
+             None, None, 0, C.byref(o), None) == _lib.RK_OK
+    o.reserved[2] = 1
+    assert f(prob.handle, 8, y.data_ptr(), y.data_ptr(), g.data_ptr(), 0.0, 1.0, 1e-6, 0.0, None,
+             None, None, 0, C.byref(o), None) == _lib.RK_EINVAL
+    assert b"reserved" in L.rk_last_error()
     torch.cuda.synchronize()
 
 
