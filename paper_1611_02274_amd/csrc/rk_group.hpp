@@ -1067,6 +1067,225 @@ constexpr int group_lds_doubles() {
   return kGroups<GP> * GP::kLdsPerSystem;
 }
 
+// A group problem whose RKCK integration runs attempt by attempt
+// (GP::kAttemptDriver): all six evaluations of an attempt in one straight
+// sequence, the groups of a wave refilled between attempts.  For a cheap
+// right-hand side with many groups per wave (Pleiades: eight) this beats the
+// evaluation-granular state machine, whose per-evaluation dispatch then costs
+// more than the evaluation.
+template <class GP, class = void>
+struct GroupAttemptDriver {
+  static constexpr bool value = false;
+};
+template <class GP>
+struct GroupAttemptDriver<GP, std::void_t<decltype(GP::kAttemptDriver)>> {
+  static constexpr bool value = GP::kAttemptDriver;
+};
+
+// RKCK by attempts: the same arithmetic, in the same order, as GRkck.
+template <class GP>
+struct GRkckAttempt {
+  static constexpr int S = GP::S;
+  typename GP::Lane L;
+  double y[S], F[S];
+  double t, h, h_want;
+  int64_t attempts;
+  int32_t n_acc, n_rej, n_rhs, status;
+  bool fvalid, cut;
+
+  __device__ void begin(const Ctl& c) {
+    t = c.t0;
+    h = 0.5 * c.hmax;
+    h_want = h;
+    cut = false;
+    fvalid = false;
+    status = kSysOk;
+    attempts = 0;
+    n_acc = n_rej = n_rhs = 0;
+  }
+
+  // One attempt; false when the integration has ended.
+  __device__ bool attempt(const Grp<GP>& x, const Ctl& c) {
+    if (attempts >= c.max_steps) {
+      status = kSysMaxSteps;
+      return false;
+    }
+    h_want = h;
+    h = fmin(c.t1 - t, h);
+    if (!fvalid) {
+      group_rhs<GP>(L, x, y, F);
+      ++n_rhs;
+      fvalid = true;
+    }
+    double k1[S], k2[S], k3[S], k4[S], k5[S], z[S], f[S], yt[S], ye[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      k1[i] = h * F[i];
+      z[i] = y[i] + ck::b21 * k1[i];
+    }
+    group_rhs<GP>(L, x, z, f);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      k2[i] = h * f[i];
+      z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
+    }
+    group_rhs<GP>(L, x, z, f);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      k3[i] = h * f[i];
+      z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
+    }
+    group_rhs<GP>(L, x, z, f);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      k4[i] = h * f[i];
+      z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
+    }
+    group_rhs<GP>(L, x, z, f);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      k5[i] = h * f[i];
+      z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
+             ck::b65 * k5[i];
+    }
+    group_rhs<GP>(L, x, z, f);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const double k6 = h * f[i];
+      yt[i] = y[i] + ck::c1 * k1[i] + ck::c3 * k3[i] + ck::c4 * k4[i] + ck::c6 * k6;
+      ye[i] = 0.0 + ck::e1 * k1[i] + ck::e3 * k3[i] + ck::e4 * k4[i] + ck::e5 * k5[i] +
+              ck::e6 * k6;
+    }
+    n_rhs += 5;
+    ++attempts;
+    double a[S];
+    bool nan_flag = false;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      nan_flag = nan_flag || (owns<GP>(x, i) && crm::is_nan(ye[i]));
+      a[i] = fabs(ye[i] / (fabs(y[i]) + fabs(h * F[i]) + c.delta));
+    }
+    nan_flag = group_any(x, nan_flag);
+    double err = group_fmax<GP>(x, a);
+    err = err / c.rtol;
+    if ((err > 1.0) || crm::is_nan(err) || nan_flag) {
+      ++n_rej;
+      if (crm::is_nan(err) || nan_flag)
+        h = h * kP1;
+      else
+        h = fmax(kSafety * h * crm::pow_minus_quarter(err), kP1 * h);
+      if (!(h >= kRkckHmin)) {
+        status = kSysHmin;
+        return false;
+      }
+    } else {
+      cut = h < h_want;
+      t += h;
+      const double hn = (err > kErrCon) ? kSafety * h * crm::pow_minus_fifth(err) : h * 5.0;
+      h = fmax(kRkckHmin, fmin(c.hmax, hn));
+      gcopy<GP>(y, yt);
+      ++n_acc;
+      fvalid = false;
+      if (!group_all_finite<GP>(x, y)) {
+        status = kSysNonFinite;
+        return false;
+      }
+    }
+    return t < c.t1;
+  }
+
+  __device__ void stats(int32_t (&st)[kNStats]) const {
+    st[kStAccept] = n_acc;
+    st[kStReject] = n_rej;
+    st[kStRhs] = n_rhs;
+    st[kStSrCalls] = 0;
+    st[kStPowIters] = 0;
+    st[kStMaxStages] = 6;
+  }
+};
+
+// The attempt-granular loop for such problems: a group takes a system, runs
+// attempts until it ends, and the wave refills idle groups between attempts.
+template <class GP>
+__device__ void group_attempt_finish(const GRkckAttempt<GP>& D, const Grp<GP>& x, int64_t n,
+                                     int64_t i, double* y1, int32_t* status, int32_t* stats,
+                                     double* carry) {
+  if (carry && x.r == 0) {
+    carry[(int64_t)kCarryValid * n + i] = D.status == kSysOk ? 1.0 : 0.0;
+    carry[(int64_t)kCarryH * n + i] = D.cut ? D.h_want : D.h;
+  }
+  if (y1)
+#pragma unroll
+    for (int m = 0; m < GP::S; ++m) {
+      const int k = x.sp[m];
+      if (k >= 0) y1[(int64_t)k * n + i] = D.y[m];
+    }
+  if (x.r == 0) {
+    int32_t st[kNStats];
+    D.stats(st);
+    if (status) status[i] = D.status;
+    if (stats)
+#pragma unroll
+      for (int r = 0; r < kNStats; ++r) stats[(int64_t)r * n + i] = st[r];
+  }
+}
+
+template <class GP>
+__device__ void group_attempt_loop(const typename GP::Params& prm, int64_t n, const double* y0,
+                                   double* y1, const double* g, const Ctl& c, int32_t* status,
+                                   int32_t* stats, unsigned long long* queue, double* lds,
+                                   const int32_t* order, double* carry) {
+  const int lane = threadIdx.x;
+  const Grp<GP> x = group_of<GP>(lds);
+  const int first_lane = lane - x.r;
+  GRkckAttempt<GP> D;
+  int64_t i = -1;
+  bool active = false, retired = false;
+  for (;;) {
+    const bool idle = !active && !retired;
+    const unsigned long long idle_mask = __ballot(idle);
+    const bool refill =
+        idle_mask && (__popcll(idle_mask) >= c.refill || !__ballot(active));
+    const bool need = refill && idle;
+    const unsigned long long need_mask = refill ? idle_mask : 0ull;
+    if (need_mask) {
+      const int leader = __ffsll((long long)need_mask) - 1;
+      unsigned long long base = 0;
+      if (lane == leader)
+        base = atomicAdd(queue, (unsigned long long)(__popcll(need_mask) / GP::kL));
+      base = __shfl(base, leader);
+      if (need) {
+        const unsigned long long below = need_mask & ((1ull << first_lane) - 1ull);
+        const unsigned long long idx = base + (unsigned long long)(__popcll(below) / GP::kL);
+        if (idx < (unsigned long long)n) {
+          i = order ? (int64_t)order[idx] : (int64_t)idx;
+          GP::init(D.L, prm, g, i, n, x);
+#pragma unroll
+          for (int m = 0; m < GP::S; ++m) {
+            const int k = x.sp[m];
+            D.y[m] = k >= 0 ? y0[(int64_t)k * n + i] : 0.0;
+          }
+          D.begin(c);
+          active = D.t < c.t1;
+          // the carried step applies to an integration that has a step to take
+          if (active && carry && carry[(int64_t)kCarryValid * n + i] != 0.0) {
+            D.h = carry[(int64_t)kCarryH * n + i];
+            D.h_want = D.h;
+          }
+          if (!active) group_attempt_finish<GP>(D, x, n, i, y1, status, stats, carry);
+        } else {
+          retired = true;
+        }
+      }
+    }
+    if (!__ballot(!retired)) break;
+    if (active && !D.attempt(x, c)) {
+      group_attempt_finish<GP>(D, x, n, i, y1, status, stats, carry);
+      active = false;
+    }
+  }
+}
+
 // Default of Ctl::align: on the 53-species network at 2^16 systems the RKC
 // kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5, the RKCK
 // kernel 1111 / 1096 / 1081 / 1089 ms with none / 1 / 5 / 8 (32 species, four
@@ -1087,6 +1306,10 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
                                       double* y1, const double* g, const Ctl& c, int32_t* status,
                                       int32_t* stats, unsigned long long* queue, double* lds,
                                       const int32_t* order, double* carry) {
+  if constexpr (Method == kMethodRkck && GroupAttemptDriver<GP>::value) {
+    group_attempt_loop<GP>(prm, n, y0, y1, g, c, status, stats, queue, lds, order, carry);
+    return;
+  }
   const int lane = threadIdx.x;
   const Grp<GP> x = group_of<GP>(lds);
   const int first_lane = lane - x.r;
