@@ -109,12 +109,12 @@ typedef struct {
                            and the isothermal networks of up to 16 species, RK_EUNSUPPORTED
                            otherwise and for taped integrations and batches); unused by
                            RKCK */
-  int32_t group_align;  /* group schedule: a group whose next step is its error estimate and
-                           controller waits while another group of its wave is at most this
-                           many evaluations from its own, so that the wave runs that code
-                           once for both (results are unchanged); 0: the default (RKCK 5,
-                           RKC 1; no waiting with the energy equation), < 0: never
-                           wait */
+  int32_t group_align;  /* group schedule, RKC: a group whose next step is its error
+                           estimate and controller waits while another group of its wave is
+                           at most this many evaluations from its own, so that the wave runs
+                           that code once for both (results are unchanged); 0: the default
+                           (1; no waiting with the energy equation), < 0: never wait.
+                           Unused by RKCK, whose groups run whole attempts in step. */
   int32_t reserved[3];  /* set to 0 */
 } rk_options;
 

@@ -467,190 +467,17 @@ __device__ void gcopy(double (&d)[GP::S], const double (&s)[GP::S]) {
   for (int m = 0; m < GP::S; ++m) d[m] = s[m];
 }
 
-// The group drivers are state machines at right-hand-side granularity: a
-// driver always holds the argument z of its next evaluation, and advance()
-// consumes the value f(z), runs the method's arithmetic up to the next
-// evaluation it needs (or the end of the integration) and sets z again.  The
-// persistent loop evaluates every active group's f(z) at one place, so the
-// groups of a wave evaluate together whatever step, stage or power iteration
-// each is in, and a group that finishes takes a new system at the next
-// evaluation.  The operations and their order are those of the one-lane
-// drivers (rk_device.hpp), hence the same bits.
-
-// ------------------------------------------------------------------- RKCK
-template <class GP>
-struct GRkck {
-  static constexpr int S = GP::S;
-  typename GP::Lane L;
-  double y[S], F[S], z[S];
-  double k1[S], k2[S], k3[S], k4[S], k5[S];
-  double t, h, h_want;
-  int64_t attempts;
-  int32_t n_acc, n_rej, n_rhs, status;
-  int32_t stage;   // the pending evaluation: 1 = f(t, y), 2..6 = stage 2..6
-  bool fvalid, cut;
-
-  // Starts an integration; true when an evaluation is pending.
-  __device__ bool begin(const Grp<GP>& x, const Ctl& c) {
-    t = c.t0;
-    h = 0.5 * c.hmax;
-    h_want = h;
-    cut = false;
-    fvalid = false;
-    status = kSysOk;
-    attempts = 0;
-    n_acc = n_rej = n_rhs = 0;
-    return next_attempt(x, c);
-  }
-
-  // The start of an attempt, up to its first evaluation (false: finished).
-  __device__ bool next_attempt(const Grp<GP>& x, const Ctl& c) {
-    if (!(t < c.t1)) return false;
-    if (attempts >= c.max_steps) {
-      status = kSysMaxSteps;
-      return false;
-    }
-    h_want = h;
-    h = fmin(c.t1 - t, h);
-    if (!fvalid) {
-      gcopy<GP>(z, y);
-      stage = 1;
-      return true;
-    }
-    return first_stage();
-  }
-
-  __device__ bool first_stage() {
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      k1[i] = h * F[i];
-      z[i] = y[i] + ck::b21 * k1[i];
-    }
-    stage = 2;
-    return true;
-  }
-
-  // Consumes f(z); false when the integration has ended.
-  __device__ bool advance(const Grp<GP>& x, const Ctl& c, const double (&f)[S]) {
-    switch (stage) {
-      case 1:
-        gcopy<GP>(F, f);
-        ++n_rhs;
-        fvalid = true;
-        return first_stage();
-      case 2:
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-          k2[i] = h * f[i];
-          z[i] = y[i] + ck::b31 * k1[i] + ck::b32 * k2[i];
-        }
-        stage = 3;
-        return true;
-      case 3:
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-          k3[i] = h * f[i];
-          z[i] = y[i] + ck::b41 * k1[i] + ck::b42 * k2[i] + ck::b43 * k3[i];
-        }
-        stage = 4;
-        return true;
-      case 4:
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-          k4[i] = h * f[i];
-          z[i] = y[i] + ck::b51 * k1[i] + ck::b52 * k2[i] + ck::b53 * k3[i] + ck::b54 * k4[i];
-        }
-        stage = 5;
-        return true;
-      case 5:
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-          k5[i] = h * f[i];
-          z[i] = y[i] + ck::b61 * k1[i] + ck::b62 * k2[i] + ck::b63 * k3[i] + ck::b64 * k4[i] +
-                 ck::b65 * k5[i];
-        }
-        stage = 6;
-        return true;
-      default:
-        break;
-    }
-    // stage 6: the trial step, its error and the controller
-    double yt[S], ye[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      const double k6 = h * f[i];
-      yt[i] = y[i] + ck::c1 * k1[i] + ck::c3 * k3[i] + ck::c4 * k4[i] + ck::c6 * k6;
-      ye[i] = 0.0 + ck::e1 * k1[i] + ck::e3 * k3[i] + ck::e4 * k4[i] + ck::e5 * k5[i] +
-              ck::e6 * k6;
-    }
-    n_rhs += 5;
-    ++attempts;
-    double a[S];
-    bool nan_flag = false;
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      nan_flag = nan_flag || (owns<GP>(x, i) && crm::is_nan(ye[i]));
-      a[i] = fabs(ye[i] / (fabs(y[i]) + fabs(h * F[i]) + c.delta));
-    }
-    nan_flag = group_any(x, nan_flag);
-    double err = group_fmax<GP>(x, a);
-    err = err / c.rtol;
-    if ((err > 1.0) || crm::is_nan(err) || nan_flag) {
-      ++n_rej;
-      if (crm::is_nan(err) || nan_flag)
-        h = h * kP1;
-      else
-        h = fmax(kSafety * h * crm::pow_minus_quarter(err), kP1 * h);
-      if (!(h >= kRkckHmin)) {
-        status = kSysHmin;
-        return false;
-      }
-    } else {
-      cut = h < h_want;
-      t += h;
-      const double hn = (err > kErrCon) ? kSafety * h * crm::pow_minus_fifth(err) : h * 5.0;
-      h = fmax(kRkckHmin, fmin(c.hmax, hn));
-      gcopy<GP>(y, yt);
-      ++n_acc;
-      fvalid = false;
-      if (!group_all_finite<GP>(x, y)) {
-        status = kSysNonFinite;
-        return false;
-      }
-    }
-    return next_attempt(x, c);
-  }
-
-  // The next advance runs the error estimate and the controller.
-  __device__ bool at_error() const { return stage == 6; }
-  // Evaluations before that (0 when there already).
-  __device__ int to_error() const { return 6 - stage; }
-
-  __device__ void stats(int32_t (&st)[kNStats]) const {
-    st[kStAccept] = n_acc;
-    st[kStReject] = n_rej;
-    st[kStRhs] = n_rhs;
-    st[kStSrCalls] = 0;
-    st[kStPowIters] = 0;
-    st[kStMaxStages] = 6;
-  }
-  __device__ const double (&state() const)[S] { return y; }
-  __device__ double (&state())[S] { return y; }
-  // carried controller state (rows of the carry array), as the one-lane driver;
-  // applied before the first evaluation
-  __device__ bool load_carry(const Grp<GP>& x, const Ctl& c, const double* carry, int64_t n,
-                             int64_t i) {
-    h = carry[(int64_t)kCarryH * n + i];
-    h_want = h;
-    attempts = 0;
-    return next_attempt(x, c);
-  }
-  __device__ void store_carry(const Grp<GP>& x, double* carry, int64_t n, int64_t i) const {
-    if (x.r != 0) return;
-    carry[(int64_t)kCarryValid * n + i] = status == kSysOk ? 1.0 : 0.0;
-    carry[(int64_t)kCarryH * n + i] = cut ? h_want : h;
-  }
-};
+// The group RKC driver is a state machine at right-hand-side granularity: it
+// always holds the argument z of its next evaluation, and advance() consumes
+// the value f(z), runs the method's arithmetic up to the next evaluation it
+// needs (or the end of the integration) and sets z again.  The persistent
+// loop evaluates every active group's f(z) at one place, so the groups of a
+// wave evaluate together whatever step, stage count or power iteration each
+// is in, and a group that finishes takes a new system at the next evaluation.
+// RKCK attempts always take the same six evaluations, so its group driver
+// runs attempt by attempt (GRkckAttempt, group_attempt_loop).  The operations
+// and their order are those of the one-lane drivers (rk_device.hpp), hence
+// the same bits.
 
 // -------------------------------------------------------------------- RKC
 template <class GP>
@@ -992,7 +819,7 @@ struct GRkc {
 };
 
 template <class GP, int Method>
-using GDriverState = typename std::conditional<Method == kMethodRkck, GRkck<GP>, GRkc<GP>>::type;
+using GDriverState = GRkc<GP>;
 
 // A group's integration of one system: start (true while an evaluation is
 // pending), advance (consumes f(z)), finish.
@@ -1067,22 +894,13 @@ constexpr int group_lds_doubles() {
   return kGroups<GP> * GP::kLdsPerSystem;
 }
 
-// A group problem whose RKCK integration runs attempt by attempt
-// (GP::kAttemptDriver): all six evaluations of an attempt in one straight
-// sequence, the groups of a wave refilled between attempts.  For a cheap
-// right-hand side with many groups per wave (Pleiades: eight) this beats the
-// evaluation-granular state machine, whose per-evaluation dispatch then costs
-// more than the evaluation.
-template <class GP, class = void>
-struct GroupAttemptDriver {
-  static constexpr bool value = false;
-};
-template <class GP>
-struct GroupAttemptDriver<GP, std::void_t<decltype(GP::kAttemptDriver)>> {
-  static constexpr bool value = GP::kAttemptDriver;
-};
-
-// RKCK by attempts: the same arithmetic, in the same order, as GRkck.
+// Group RKCK attempt by attempt: all six evaluations of an attempt in one
+// straight sequence, the groups of a wave refilled between attempts.  Every
+// attempt takes the same evaluations, so the groups of a wave stay in step
+// and an evaluation-granular state machine only adds its dispatch (53
+// species at 2^16 systems: 863 against 1009 ms; Pleiades, eight groups per
+// wave, 19.6 against 34.4 ms).
+// RKCK by attempts: the arithmetic of the one-lane driver, in its order.
 template <class GP>
 struct GRkckAttempt {
   static constexpr int S = GP::S;
@@ -1286,16 +1104,17 @@ __device__ void group_attempt_loop(const typename GP::Params& prm, int64_t n, co
   }
 }
 
-// Default of Ctl::align: on the 53-species network at 2^16 systems the RKC
-// kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5, the RKCK
-// kernel 1111 / 1096 / 1081 / 1089 ms with none / 1 / 5 / 8 (32 species, four
-// groups per wave: RKC 505 / 472 / 525 / 590 ms with none / 1 / 3 / 8).  With
+// Default of Ctl::align (the RKC state machine; RKCK groups run whole
+// attempts and stay in step): on the 53-species network at 2^16 systems the
+// RKC kernel took 760 / 742 / 753 / 767 ms with no waiting / 1 / 2 / 5 (32
+// species, four groups per wave: 505 / 472 / 525 / 590 ms with none / 1 / 3 /
+// 8).  With
 // the energy equation the evaluation (an exponential per reaction) outweighs
 // the controller, and waiting costs more than it saves (53 species + T at
 // 2^18 systems: 8.54 s without, 8.71 s with 1).
 template <class GP, int Method>
 constexpr int group_align_default() {
-  return GroupThermal<GP>::value ? 0 : (Method == kMethodRkck ? 5 : 1);
+  return GroupThermal<GP>::value ? 0 : 1;
 }
 
 // Persistent loop at group granularity: as persistent_loop, with a group of
@@ -1306,7 +1125,7 @@ __device__ void group_persistent_loop(const typename GP::Params& prm, int64_t n,
                                       double* y1, const double* g, const Ctl& c, int32_t* status,
                                       int32_t* stats, unsigned long long* queue, double* lds,
                                       const int32_t* order, double* carry) {
-  if constexpr (Method == kMethodRkck && GroupAttemptDriver<GP>::value) {
+  if constexpr (Method == kMethodRkck) {
     group_attempt_loop<GP>(prm, n, y0, y1, g, c, status, stats, queue, lds, order, carry);
     return;
   }

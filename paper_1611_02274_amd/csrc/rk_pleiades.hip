@@ -89,10 +89,6 @@ struct PleiadesGroup {
   static constexpr int kLaneDoubles = 0;
   static constexpr int S = 4;
   static constexpr bool kOwnRhs = true;
-  // RKCK attempt by attempt (a cheap right-hand side and eight groups per
-  // wave: 20 ms against 34 ms for the evaluation-granular driver at 2^18
-  // systems, ten global steps)
-  static constexpr bool kAttemptDriver = true;
   static constexpr int kOffPos = 0;               // x_1..x_7, y_1..y_7
   static constexpr int kOffPair = 14;             // 1 / r_ij at i * 7 + j
   static constexpr int kOffRed = kOffPair + 50;   // norm scratch, N doubles (16-byte aligned)
